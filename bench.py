@@ -1,0 +1,160 @@
+"""Throughput of the hybrid LB/FD step on one MI355X.
+
+Default workload: the large single-GPU droplet-in-shear run, 1024 x 256 x 1024 nodes
+(268M), two Shan-Chen components, Newtonian droplet R = 64, viscoelastic matrix (L^2 = 400,
+De = 1), Ca = 0.2, FP32 populations (deviations from w rho0) and FP32 C - I, FP64
+diagnostics every 100 steps.  Synthetic seeded inputs, resident in HBM before timing.
+
+Prints one JSON line: MLUPS, ms/step, the HBM roofline of the step and the FP64 CPU
+oracle timed on a bounded sub-box of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline (LBM+FENE-P step); FP32-vs-FP64 err; sweep time-to-D"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per node and step (FP32): populations read + written
+# (2 x ncomp x 19 x 4) and C read + written (2 x 6 x 4)
+ALG_BYTES = {1: 200, 2: 352}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_lattice(lb, workloads, nx, ny, nz, zchunk=16):
+    """Create the droplet lattice and upload its fields slab by slab (host memory stays
+    bounded for the 268M-node grid)."""
+    wl0 = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(0, nx, 0, 1))
+    lat = lb.Lattice(nx, ny, nz, 2, wl0["params"])
+    lat.set_walls(wl0["walls"]["u_bottom"], wl0["walls"]["u_top"])
+    for z0 in range(0, nz, zchunk):
+        bz = min(zchunk, nz - z0)
+        w = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(0, nx, z0, bz))
+        lat.set_fields_box(0, 0, z0, nx, ny, bz, w["rho"], w["u"], w["C"])
+    lat.reset_counters()
+    return lat, wl0
+
+
+def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0):
+    """FP64 oracle on a 96 x ny x 96 sub-box window of the same workload (same per-node
+    work), stepped until about `budget_s` seconds of CPU time have passed."""
+    import oracle
+
+    bx = min(96, nx)
+    bz = min(96, nz)
+    x0 = (nx - bx) // 2
+    z0 = (nz - bz) // 2
+    wl = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(x0, bx, z0, bz))
+    o = oracle.from_workload(wl)
+    nodes = bx * ny * bz
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 50:
+            break
+    return {"value": nodes * steps / el / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of a {bx}x{ny}x{bz} window of the same droplet workload "
+                      f"({nodes} nodes, FP64, {el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--grid", type=str, default="1024x256x1024")
+    ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the multi-GPU (slab-decomposed) path is a design, "
+              "not part of this build; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1406_2686_amd as lb
+    import workloads
+
+    nx, ny, nz = (int(v) for v in args.grid.split("x"))
+    N = nx * ny * nz
+    torch.cuda.set_device(0)
+    t_init = time.perf_counter()
+    lat, wl0 = build_lattice(lb, workloads, nx, ny, nz)
+    torch.cuda.synchronize()
+    log(f"init {nx}x{ny}x{nz}: {time.perf_counter() - t_init:.1f} s")
+
+    d0 = lat.diagnostics()
+    lat.step_async(args.warmup)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+
+    stream = lat.stream
+    K = args.steps
+    every = max(1, args.diag_every)
+    ev = []
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    done = 0
+    diags = []
+    while done < K:
+        n = min(every, K - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lat.step_async(n)
+        b.record(stream)
+        ev.append((a, b, n))
+        done += n
+        if args.diag_every > 0:
+            diags.append(lat.diagnostics())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    step_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / K
+    flags = lat.flags()
+    d1 = lat.diagnostics()
+    log(f"timed {K} steps: wall {wall:.2f} s, {step_ms:.3f} ms/step (events), flags={flags}")
+
+    mlups = N * K / wall / 1e6
+    alg = ALG_BYTES[2] * N
+    achieved = alg / (step_ms * 1e-3) / 1e9
+    mass_drift = max(abs(d1["mass_A"] - d0["mass_A"]) / d0["mass_A"],
+                     abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"])
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": K, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / K, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"droplet_shear_{nx}x{ny}x{nz}", "nodes": N, "ncomp": 2,
+                   "droplet_R": wl0["meta"]["R"], "polymer": "matrix (L2=400, De=1)",
+                   "diag_every": args.diag_every, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "one step (k_moments + k_forces + k_collide)",
+                     "alg_bytes_per_node": ALG_BYTES[2], "event_ms_per_step": round(step_ms, 4)},
+        "checks": {"fault_flags": flags, "mass_drift_rel": mass_drift, "D_final": d1["D"]},
+    }
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(workloads, nx, ny, nz)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * lbfd.h -- C ABI of the MI355X (gfx950) library for the hybrid lattice-Boltzmann /
+ * finite-difference step of Gupta, Sbragaglia & Scagliarini, arXiv:1406.2686:
+ * two Shan-Chen components on a D3Q19 lattice (interaction force, BGK collision with
+ * forcing, streaming, moving-wall bounce-back) coupled to a finite-difference FENE-P
+ * conformation tensor whose stress divergence is fed back as a body force.
+ *
+ * Conventions (all calls):
+ *  - Every call returns lbfd_status; 0 is success.  No C++ exception crosses the ABI.
+ *    lbfd_last_error() returns a context-owned, NUL-terminated description of the last
+ *    failure (valid until the next call on that context).
+ *  - Geometry: x and z periodic; y is wall-normal with half-way walls at y = -1/2 and
+ *    y = ny - 1/2 (Sec. 3.1 and Sec. 4.1 set-ups: walls moving in x, periodic in x and z).
+ *  - Host field layout: FP64 structure-of-arrays [field][z][y][x], x fastest.  Symmetric
+ *    tensors are stored as 6 components (xx, yy, zz, xy, xz, yz).
+ *  - Device memory is caller-owned: the caller allocates one device buffer of
+ *    lbfd_state_bytes() bytes (256-byte aligned) and passes it to lbfd_create.  The
+ *    library never allocates or frees device memory; it keeps populations, conformation
+ *    tensor, side fields, staging and reduction scratch inside that buffer.
+ *  - All device work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *    void*, NULL = the null stream).  Calls that return host data synchronise it.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Device arithmetic is FP32 (populations stored as deviations f - w_a rho0_s, the
+ *    conformation tensor as C - I); diagnostics reduce in FP64.
+ */
+#ifndef LBFD_H
+#define LBFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbfd_status;
+#define LBFD_OK 0
+#define LBFD_EINVAL 1          /* invalid argument or parameter set                      */
+#define LBFD_ENOMEM 2          /* device buffer too small                                */
+#define LBFD_EDEVICE 3         /* HIP runtime error (message in lbfd_last_error)         */
+#define LBFD_ENONFINITE 4      /* a population or C component became NaN/Inf             */
+#define LBFD_EEXTENSIBILITY 5  /* tr C reached L^2 (FENE-P spring diverges)              */
+#define LBFD_ENOTSPD 6         /* C lost positive definiteness (a leading minor <= 0)    */
+#define LBFD_ESTATE 7          /* call out of order (e.g. step before set_fields)        */
+
+/* fault bits reported in lbfd_diag.flags and folded into the step status */
+#define LBFD_FLAG_NONFINITE 1u
+#define LBFD_FLAG_EXTENSIBILITY 2u
+#define LBFD_FLAG_NOT_SPD 4u
+
+/* which phase carries the polymer feedback (modulation m(phi) of Sec. 2, Yue et al. form) */
+#define LBFD_POLYMER_NONE 0 /* C evolves, no feedback into the fluid   */
+#define LBFD_POLYMER_A 1    /* m = f+(phi) = (1 + tanh(phi/Delta))/2   */
+#define LBFD_POLYMER_B 2    /* m = f-(phi) = (1 - tanh(phi/Delta))/2   */
+#define LBFD_POLYMER_ALL 3  /* m = 1                                    */
+
+typedef struct lbfd_ctx lbfd_ctx;
+
+typedef struct {
+    int32_t nx, ny, nz; /* lattice nodes; ny >= 3 (wall-normal), nx, nz >= 1          */
+    int32_t ncomp;      /* 1 or 2 Shan-Chen components (A, B)                          */
+} lbfd_grid;
+
+typedef struct {
+    double tau_A, tau_B;   /* BGK relaxation time in A-rich / B-rich regions (> 1/2);   */
+                           /* local tau = tau_B + (tau_A - tau_B) f+(phi)              */
+    double G;              /* Shan-Chen coupling (Sec. 2, eq. SCforce)                  */
+    double delta;          /* smoothing width of f+-(phi) (Sec. 2, eq. smoothingvisco)  */
+    double rho0[2];        /* storage shift per component (populations kept as f - w rho0) */
+    int32_t polymer_phase; /* LBFD_POLYMER_*                                           */
+    int32_t reserved;
+    double eta_p;          /* polymer viscosity (Sec. 2, eq. NS)                        */
+    double tau_p;          /* polymer relaxation time in lattice steps (> 0)            */
+    double L2;             /* FENE-P maximum extension squared (> 3)                    */
+} lbfd_params;
+
+/* FP64 diagnostics of the current state (droplet shape per Sec. 4.1: D = (a-b)/(a+b),
+ * theta = angle of the major axis with the flow direction x, from the x-y block of the
+ * second moments of w = max(phi, 0)). */
+typedef struct {
+    double mass[2];         /* sum of rho per component                               */
+    double momentum[3];     /* sum of rho u (u with the half-force shift)             */
+    double W;               /* sum of w                                               */
+    double centroid[3];     /* sum(w x)/W                                             */
+    double M[6];            /* second moments about the centroid / W (xx,yy,zz,xy,xz,yz) */
+    double D;               /* deformation parameter                                  */
+    double theta_deg;       /* orientation in degrees                                 */
+    double min_L2_minus_trC;
+    double min_minor;       /* smallest leading principal minor of C                  */
+    double max_u;           /* max |u|                                                */
+    uint32_t flags;         /* LBFD_FLAG_* seen since the last lbfd_set_fields         */
+    uint32_t reserved;
+    int64_t step;           /* steps taken since lbfd_set_fields                       */
+} lbfd_diag;
+
+/* Device bytes needed for a grid (populations x2, C x2, side fields, staging, scratch).
+ * EINVAL for an invalid grid. */
+lbfd_status lbfd_state_bytes(const lbfd_grid* grid, uint64_t* bytes);
+
+/* Create a context bound to a caller-owned device buffer `dev_state` of `bytes` bytes
+ * on the current HIP device and to `hip_stream`.  Validates the grid and the
+ * parameters (EINVAL) and the buffer size (ENOMEM).  *out is NULL on failure. */
+lbfd_status lbfd_create(const lbfd_grid* grid, const lbfd_params* params, void* dev_state,
+                        uint64_t bytes, void* hip_stream, lbfd_ctx** out);
+
+/* Replace the parameter set (same validation as create).  Takes effect at the next step. */
+lbfd_status lbfd_set_params(lbfd_ctx* ctx, const lbfd_params* params);
+
+/* Wall velocities (bottom at y = -1/2, top at y = ny - 1/2).  Only tangential motion:
+ * a non-zero y component is EINVAL (Sec. 3.1: walls slide in x). */
+lbfd_status lbfd_set_walls(lbfd_ctx* ctx, const double u_bottom[3], const double u_top[3]);
+
+/* Initialise populations to the equilibrium E(rho_s, u) (no non-equilibrium part) and
+ * C as given, on the whole grid.  rho: ncomp x N, u: 3 x N, C: 6 x N host arrays.
+ * Checks finiteness, positive definiteness and tr C < L^2 on the host (EINVAL).
+ * Resets the step counter and the fault flags. */
+lbfd_status lbfd_set_fields(lbfd_ctx* ctx, const double* rho, const double* u, const double* C);
+
+/* Same on the sub-box [x0, x0+bx) x [y0, y0+by) x [z0, z0+bz); arrays are ncomp x B,
+ * 3 x B, 6 x B with B = bx*by*bz in [z][y][x] order.  Does not reset the counters
+ * (call lbfd_reset_counters after the last box). */
+lbfd_status lbfd_set_fields_box(lbfd_ctx* ctx, int32_t x0, int32_t y0, int32_t z0, int32_t bx,
+                                int32_t by, int32_t bz, const double* rho, const double* u,
+                                const double* C);
+lbfd_status lbfd_reset_counters(lbfd_ctx* ctx);
+
+/* Advance nsteps >= 0 time steps.  Returns ENONFINITE / EEXTENSIBILITY / ENOTSPD (in
+ * that priority) if the device fault flags were raised during this call; the state
+ * then holds the result of all nsteps steps and is not repaired. */
+lbfd_status lbfd_step(lbfd_ctx* ctx, int64_t nsteps);
+
+/* Enqueue nsteps steps without synchronising or reading the fault flags (for timing
+ * and graph capture).  Fault flags accumulate and are reported by the next
+ * lbfd_step / lbfd_diagnostics / lbfd_get_flags. */
+lbfd_status lbfd_step_async(lbfd_ctx* ctx, int64_t nsteps);
+lbfd_status lbfd_get_flags(lbfd_ctx* ctx, uint32_t* flags);
+
+/* Macroscopic fields of the current state: rho (ncomp x N), u (3 x N, including the
+ * half-force shift of Sec. 2, eq. equilibrium:vel) and C (6 x N).  Any pointer may be
+ * NULL.  Synchronises the stream. */
+lbfd_status lbfd_get_fields(lbfd_ctx* ctx, double* rho, double* u, double* C);
+lbfd_status lbfd_get_fields_box(lbfd_ctx* ctx, int32_t x0, int32_t y0, int32_t z0, int32_t bx,
+                                int32_t by, int32_t bz, double* rho, double* u, double* C);
+
+/* FP64 diagnostics record of the current state.  Synchronises the stream. */
+lbfd_status lbfd_diagnostics(lbfd_ctx* ctx, lbfd_diag* out);
+
+/* Raw checkpoint of the device state (FP32 populations and C - I, step counter, flags):
+ * lbfd_checkpoint_bytes gives the size; get copies device -> host, set host -> device. */
+lbfd_status lbfd_checkpoint_bytes(lbfd_ctx* ctx, uint64_t* bytes);
+lbfd_status lbfd_get_state(lbfd_ctx* ctx, void* host, uint64_t bytes);
+lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
+
+/* Library build/version string (static). */
+const char* lbfd_version(void);
+
+void lbfd_destroy(lbfd_ctx* ctx);
+const char* lbfd_last_error(const lbfd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBFD_H */

@@ -77,8 +77,14 @@ def lib():
         L.orc_fenep_kinematic.restype = ctypes.c_int
         L.orc_get_C.argtypes = [P, D]
         L.orc_set_C.argtypes = [P, D]
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses (OMP_NUM_THREADS or all cores)."""
+    return int(lib().orc_threads())
 
 
 def _dp(a: np.ndarray):

@@ -630,3 +630,10 @@ int orc_fenep_kinematic(orc_t *o, const double *u, long nsteps) {
 
 void orc_get_C(const orc_t *o, double *C) { memcpy(C, o->C, sizeof(double) * 6 * o->N); }
 void orc_set_C(orc_t *o, const double *C) { memcpy(o->C, C, sizeof(double) * 6 * o->N); }
+
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

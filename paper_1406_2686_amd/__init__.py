@@ -1,0 +1,262 @@
+"""Python binding of liblbfd, the gfx950 library for the hybrid lattice-Boltzmann /
+finite-difference step of arXiv:1406.2686 (Shan-Chen D3Q19 + FENE-P).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch supplies the device memory (one caller-owned buffer per lattice) and the HIP
+stream.  If the compiled library is missing this module raises at import; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbfd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_1406_2686_amd/build.py` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EEXTENSIBILITY, ENOTSPD, ESTATE = range(8)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENONFINITE",
+                5: "EEXTENSIBILITY", 6: "ENOTSPD", 7: "ESTATE"}
+FLAG_NONFINITE, FLAG_EXTENSIBILITY, FLAG_NOT_SPD = 1, 2, 4
+POLYMER = {"none": 0, "A": 1, "B": 2, "all": 3}
+
+
+class LbfdError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("ncomp", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tau_A", ctypes.c_double), ("tau_B", ctypes.c_double), ("G", ctypes.c_double),
+                ("delta", ctypes.c_double), ("rho0", ctypes.c_double * 2),
+                ("polymer_phase", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("eta_p", ctypes.c_double), ("tau_p", ctypes.c_double), ("L2", ctypes.c_double)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double * 2), ("momentum", ctypes.c_double * 3),
+                ("W", ctypes.c_double), ("centroid", ctypes.c_double * 3),
+                ("M", ctypes.c_double * 6), ("D", ctypes.c_double), ("theta_deg", ctypes.c_double),
+                ("min_L2_minus_trC", ctypes.c_double), ("min_minor", ctypes.c_double),
+                ("max_u", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("step", ctypes.c_int64)]
+
+    def to_dict(self):
+        return {"mass_A": self.mass[0], "mass_B": self.mass[1], "mom_x": self.momentum[0],
+                "mom_y": self.momentum[1], "mom_z": self.momentum[2], "W": self.W,
+                "xc": self.centroid[0], "yc": self.centroid[1], "zc": self.centroid[2],
+                "Mxx": self.M[0], "Myy": self.M[1], "Mzz": self.M[2], "Mxy": self.M[3],
+                "Mxz": self.M[4], "Myz": self.M[5], "D": self.D, "theta_deg": self.theta_deg,
+                "min_L2_minus_trC": self.min_L2_minus_trC, "min_minor": self.min_minor,
+                "max_u": self.max_u, "flags": int(self.flags), "step": int(self.step)}
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+
+def _sig(name, args, res=ctypes.c_int32):
+    fn = getattr(_lib, name)
+    fn.argtypes = args
+    fn.restype = res
+    return fn
+
+
+_sig("lbfd_state_bytes", [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_uint64)])
+_sig("lbfd_create", [ctypes.POINTER(Grid), ctypes.POINTER(Params), _P, ctypes.c_uint64, _P,
+                     ctypes.POINTER(_P)])
+_sig("lbfd_set_params", [_P, ctypes.POINTER(Params)])
+_sig("lbfd_set_walls", [_P, _D, _D])
+_sig("lbfd_set_fields", [_P, _D, _D, _D])
+_sig("lbfd_set_fields_box", [_P, _I32, _I32, _I32, _I32, _I32, _I32, _D, _D, _D])
+_sig("lbfd_reset_counters", [_P])
+_sig("lbfd_step", [_P, _I64])
+_sig("lbfd_step_async", [_P, _I64])
+_sig("lbfd_get_flags", [_P, ctypes.POINTER(ctypes.c_uint32)])
+_sig("lbfd_get_fields", [_P, _D, _D, _D])
+_sig("lbfd_get_fields_box", [_P, _I32, _I32, _I32, _I32, _I32, _I32, _D, _D, _D])
+_sig("lbfd_diagnostics", [_P, ctypes.POINTER(Diag)])
+_sig("lbfd_checkpoint_bytes", [_P, ctypes.POINTER(ctypes.c_uint64)])
+_sig("lbfd_get_state", [_P, _P, ctypes.c_uint64])
+_sig("lbfd_set_state", [_P, _P, ctypes.c_uint64])
+_sig("lbfd_version", [], ctypes.c_char_p)
+_sig("lbfd_destroy", [_P], None)
+_sig("lbfd_last_error", [_P], ctypes.c_char_p)
+
+
+def raw():
+    """The ctypes handle of liblbfd (for ABI-level tests)."""
+    return _lib
+
+
+def version() -> str:
+    return _lib.lbfd_version().decode()
+
+
+def _dp(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def make_params(tau_A=1.0, tau_B=1.0, G=0.0, delta=0.1, rho0=(1.0, 0.0), polymer_phase="none",
+                eta_p=0.0, tau_p=1000.0, L2=100.0, **_ignored) -> Params:
+    ph = POLYMER[polymer_phase] if isinstance(polymer_phase, str) else int(polymer_phase)
+    r0 = list(rho0) + [0.0] * (2 - len(rho0))
+    return Params(float(tau_A), float(tau_B), float(G), float(delta),
+                  (ctypes.c_double * 2)(*r0), ph, 0, float(eta_p), float(tau_p), float(L2))
+
+
+def state_bytes(nx, ny, nz, ncomp) -> int:
+    g = Grid(nx, ny, nz, ncomp)
+    b = ctypes.c_uint64(0)
+    st = _lib.lbfd_state_bytes(ctypes.byref(g), ctypes.byref(b))
+    if st != OK:
+        raise LbfdError(st, "invalid grid")
+    return int(b.value)
+
+
+class Lattice:
+    """One lattice on the current GPU.  Device state lives in a torch uint8 tensor."""
+
+    def __init__(self, nx, ny, nz, ncomp, params: Params | dict, device="cuda", stream=None):
+        import torch
+
+        self.nx, self.ny, self.nz, self.ncomp = int(nx), int(ny), int(nz), int(ncomp)
+        self.N = self.nx * self.ny * self.nz
+        self.grid = Grid(self.nx, self.ny, self.nz, self.ncomp)
+        nbytes = state_bytes(self.nx, self.ny, self.nz, self.ncomp)
+        self.device = torch.device(device)
+        self._buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._buf.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        p = params if isinstance(params, Params) else make_params(**params)
+        h = _P()
+        with torch.cuda.device(self.device):
+            st = _lib.lbfd_create(ctypes.byref(self.grid), ctypes.byref(p), _P(aligned),
+                                  ctypes.c_uint64(nbytes), _P(self._stream.cuda_stream),
+                                  ctypes.byref(h))
+        if st != OK:
+            raise LbfdError(st, "lbfd_create failed")
+        self._h = h
+
+    # -- helpers
+    def _check(self, st):
+        if st != OK:
+            raise LbfdError(st, _lib.lbfd_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lbfd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def set_params(self, params):
+        p = params if isinstance(params, Params) else make_params(**params)
+        self._check(_lib.lbfd_set_params(self._h, ctypes.byref(p)))
+
+    def set_walls(self, u_bottom, u_top):
+        ub = np.ascontiguousarray(u_bottom, dtype=np.float64)
+        ut = np.ascontiguousarray(u_top, dtype=np.float64)
+        self._check(_lib.lbfd_set_walls(self._h, _dp(ub), _dp(ut)))
+
+    def set_fields(self, rho, u, C):
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.ncomp, self.N)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, self.N)
+        C = np.ascontiguousarray(C, dtype=np.float64).reshape(6, self.N)
+        self._check(_lib.lbfd_set_fields(self._h, _dp(rho), _dp(u), _dp(C)))
+
+    def set_fields_box(self, x0, y0, z0, bx, by, bz, rho, u, C):
+        B = bx * by * bz
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(self.ncomp, B)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, B)
+        C = np.ascontiguousarray(C, dtype=np.float64).reshape(6, B)
+        self._check(_lib.lbfd_set_fields_box(self._h, x0, y0, z0, bx, by, bz, _dp(rho), _dp(u),
+                                             _dp(C)))
+
+    def reset_counters(self):
+        self._check(_lib.lbfd_reset_counters(self._h))
+
+    def step(self, n: int):
+        self._check(_lib.lbfd_step(self._h, int(n)))
+
+    def step_status(self, n: int) -> int:
+        """Like step() but returns the status code instead of raising."""
+        return int(_lib.lbfd_step(self._h, int(n)))
+
+    def step_async(self, n: int):
+        self._check(_lib.lbfd_step_async(self._h, int(n)))
+
+    def flags(self) -> int:
+        f = ctypes.c_uint32(0)
+        self._check(_lib.lbfd_get_flags(self._h, ctypes.byref(f)))
+        return int(f.value)
+
+    def get_fields(self):
+        rho = np.zeros((self.ncomp, self.N))
+        u = np.zeros((3, self.N))
+        C = np.zeros((6, self.N))
+        self._check(_lib.lbfd_get_fields(self._h, _dp(rho), _dp(u), _dp(C)))
+        return rho, u, C
+
+    def get_fields_box(self, x0, y0, z0, bx, by, bz):
+        B = bx * by * bz
+        rho = np.zeros((self.ncomp, B))
+        u = np.zeros((3, B))
+        C = np.zeros((6, B))
+        self._check(_lib.lbfd_get_fields_box(self._h, x0, y0, z0, bx, by, bz, _dp(rho), _dp(u),
+                                             _dp(C)))
+        return rho, u, C
+
+    def diagnostics(self) -> dict:
+        d = Diag()
+        self._check(_lib.lbfd_diagnostics(self._h, ctypes.byref(d)))
+        return d.to_dict()
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_uint64(0)
+        self._check(_lib.lbfd_checkpoint_bytes(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(_lib.lbfd_get_state(self._h, ctypes.cast(buf, _P), n))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(_lib.lbfd_set_state(self._h, ctypes.cast(buf, _P), ctypes.c_uint64(len(blob))))
+
+
+def from_workload(wl, device="cuda") -> Lattice:
+    """Create a lattice from a workload dict (see workloads.py) and upload its fields."""
+    g = wl["grid"]
+    lat = Lattice(g["nx"], g["ny"], g["nz"], g["ncomp"], wl["params"], device=device)
+    lat.set_walls(wl["walls"]["u_bottom"], wl["walls"]["u_top"])
+    lat.set_fields(wl["rho"], wl["u"], wl["C"])
+    return lat

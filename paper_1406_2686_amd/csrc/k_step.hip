@@ -1,0 +1,383 @@
+// k_step.hip -- one time step of the hybrid LB/FD method on gfx950, three passes:
+//
+//   k_moments : populations -> delta rho_s, j                       (Sec. 2, moments)
+//   k_forces  : Shan-Chen force (Sec. 2, eq. SCforce), polymer-stress divergence of
+//               T = (eta_p/tau_p) m(phi) (f(r) C - I) (FENE-P feedback, modulated by
+//               f+-(phi)), species split F_s = g_s + (rho_s/rho) F_p (weight of eq.
+//               MODEtransformation), half-force velocity u (eq. equilibrium:vel)
+//   k_collide : BGK collision with the forcing source (eq. LB, Lambda = I/tau(phi)),
+//               push streaming with half-way moving-wall bounce-back, and the explicit
+//               FENE-P step C += -(u.grad)_upwind C + G^T C + C G - (f C - I)/tau_p with
+//               G_ij = d_i u_j (eq. FENE), all reading time level n only.
+//
+// Every pass is a one-thread-per-node map over [z][y][x] with x fastest, so each
+// wavefront reads and writes 64 consecutive FP32 words per population plane.  Blocks
+// are remapped so that each XCD (8 per MI355X) owns one contiguous range of the
+// lattice; neighbour reads in y and z then hit the same XCD's L2.
+#include "d3q19.h"
+#include "lbfd_internal.h"
+
+namespace lbfd {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t per = nb >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ int64_t node_id() {
+    return xcd_remap(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+}
+
+// delta rho and momentum of the populations of one component at node n.  Opposite
+// pairs are differenced first (c_{a+1} = -c_a), which keeps j free of the rho0 shift.
+__device__ __forceinline__ void pop_moments(const float* __restrict__ h, int64_t N, int64_t n,
+                                            float& dr, float& jx, float& jy, float& jz) {
+    float f[kQ];
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) f[a] = h[a * N + n];
+    float s = f[0];
+#pragma unroll
+    for (int a = 1; a < kQ; a += 2) s += f[a] + f[a + 1];
+    dr = s;
+#pragma unroll
+    for (int a = 1; a < kQ; a += 2) {
+        const float d = f[a] - f[a + 1];
+        jx += cx(a) * d;
+        jy += cy(a) * d;
+        jz += cz(a) * d;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_moments(DevParams p, const float* __restrict__ h,
+                                                    float* __restrict__ mom) {
+    const int64_t n = node_id();
+    if (n >= p.N) return;
+    const int64_t N = p.N;
+    float jx = 0.f, jy = 0.f, jz = 0.f;
+    for (int s = 0; s < p.nc; ++s) {
+        float dr;
+        pop_moments(h + (int64_t)s * kQ * N, N, n, dr, jx, jy, jz);
+        mom[s * N + n] = dr;
+    }
+    mom[(p.nc + 0) * N + n] = jx;
+    mom[(p.nc + 1) * N + n] = jy;
+    mom[(p.nc + 2) * N + n] = jz;
+}
+
+// order parameter and feedback modulation
+__device__ __forceinline__ float phase_phi(const DevParams& p, float rA, float rB) {
+    return p.nc == 2 ? (rA - rB) / (rA + rB) : 1.0f;
+}
+__device__ __forceinline__ float modulation(const DevParams& p, float phi) {
+    if (p.phase == 3) return 1.0f;
+    if (p.phase == 0) return 0.0f;
+    const float t = tanhf(phi * p.inv_delta);
+    return p.phase == 1 ? 0.5f * (1.0f + t) : 0.5f * (1.0f - t);
+}
+
+// Polymer stress of one (possibly ghost) node from D = C - I and phi:
+// T = (eta_p/tau_p) m (f D + (f - 1) I), f = (L^2 - 3)/(L^2 - 3 - tr D).
+__device__ __forceinline__ void stress(const DevParams& p, const float d[6], float phi, float T[6],
+                                       unsigned& bad) {
+    const float trd = d[0] + d[1] + d[2];
+    const float den = p.L2m3 - trd;
+    if (!(den > 0.0f)) bad |= 2u;
+    const float inv = 1.0f / den;
+    const float f = p.L2m3 * inv;
+    const float fm1 = trd * inv;
+    const float pre = p.pstress * modulation(p, phi);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) T[k] = pre * (f * d[k] + (k < 3 ? fm1 : 0.0f));
+}
+
+__global__ __launch_bounds__(kBlock) void k_forces(DevParams p, const float* __restrict__ mom,
+                                                   const float* __restrict__ D,
+                                                   float* __restrict__ uF,
+                                                   unsigned* __restrict__ flags) {
+    const int64_t n = node_id();
+    if (n >= p.N) return;
+    const int64_t N = p.N;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int x = (int)(n % nx);
+    const int64_t r = n / nx;
+    const int y = (int)(r % ny);
+    const int z = (int)(r / ny);
+
+    const float dA = mom[n];
+    const float dB = p.nc == 2 ? mom[N + n] : 0.0f;
+    const float rA = p.rho0[0] + dA;
+    const float rB = p.nc == 2 ? p.rho0[1] + dB : 0.0f;
+    const float rho = rA + rB;
+    float j[3] = {mom[(p.nc + 0) * N + n], mom[(p.nc + 1) * N + n], mom[(p.nc + 2) * N + n]};
+
+    float gA[3] = {0.f, 0.f, 0.f}, gB[3] = {0.f, 0.f, 0.f};
+    if (p.nc == 2 && p.G != 0.0f) {
+        // s_s = sum_a w_a rho_s(x + c_a) c_a, summed over opposite pairs as differences
+        float sA[3] = {0.f, 0.f, 0.f}, sB[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 1; a < kQ; a += 2) {
+            const int xp = wrap1(x + cx(a), nx), yp = clampy(y + cy(a), ny), zp = wrap1(z + cz(a), nz);
+            const int xm = wrap1(x - cx(a), nx), ym = clampy(y - cy(a), ny), zm = wrap1(z - cz(a), nz);
+            const int64_t np_ = ((int64_t)zp * ny + yp) * nx + xp;
+            const int64_t nm_ = ((int64_t)zm * ny + ym) * nx + xm;
+            const float da = wgt(a) * (mom[np_] - mom[nm_]);
+            const float db = wgt(a) * (mom[N + np_] - mom[N + nm_]);
+            sA[0] += cx(a) * da; sA[1] += cy(a) * da; sA[2] += cz(a) * da;
+            sB[0] += cx(a) * db; sB[1] += cy(a) * db; sB[2] += cz(a) * db;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            gA[d] = -p.G * rA * sB[d];
+            gB[d] = -p.G * rB * sA[d];
+        }
+    }
+
+    float Fp[3] = {0.f, 0.f, 0.f};
+    unsigned bad = 0u;
+    if (p.pstress != 0.0f && p.phase != 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            float Tp[6], Tm[6];
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int sg = side == 0 ? 1 : -1;
+                int xn = x, yn = y, zn = z;
+                if (i == 0) xn = wrap1(x + sg, nx);
+                if (i == 1) yn = y + sg;
+                if (i == 2) zn = wrap1(z + sg, nz);
+                float dv[6];
+                float phi;
+                if (yn >= 0 && yn < ny) {
+                    const int64_t m = ((int64_t)zn * ny + yn) * nx + xn;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) dv[k] = D[k * N + m];
+                    const float a_ = p.rho0[0] + mom[m];
+                    const float b_ = p.nc == 2 ? p.rho0[1] + mom[N + m] : 0.0f;
+                    phi = phase_phi(p, a_, b_);
+                } else {
+                    // linear extrapolation of C across the wall; phi copies the wall layer
+                    const int y0 = yn < 0 ? 0 : ny - 1;
+                    const int y1 = yn < 0 ? 1 : ny - 2;
+                    const int64_t m0 = ((int64_t)zn * ny + y0) * nx + xn;
+                    const int64_t m1 = ((int64_t)zn * ny + y1) * nx + xn;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) dv[k] = 2.0f * D[k * N + m0] - D[k * N + m1];
+                    const float a_ = p.rho0[0] + mom[m0];
+                    const float b_ = p.nc == 2 ? p.rho0[1] + mom[N + m0] : 0.0f;
+                    phi = phase_phi(p, a_, b_);
+                }
+                if (side == 0) stress(p, dv, phi, Tp, bad);
+                else stress(p, dv, phi, Tm, bad);
+            }
+#pragma unroll
+            for (int jd = 0; jd < 3; ++jd) Fp[jd] += 0.5f * (Tp[sidx(i, jd)] - Tm[sidx(i, jd)]);
+        }
+    }
+
+    const float inv_rho = 1.0f / rho;
+    const float shA = rA * inv_rho, shB = rB * inv_rho;
+    float FA[3], FB[3], u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        FA[d] = gA[d] + shA * Fp[d];
+        FB[d] = gB[d] + shB * Fp[d];
+        u[d] = (j[d] + 0.5f * (FA[d] + FB[d])) * inv_rho;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        uF[d * N + n] = u[d];
+        uF[(3 + d) * N + n] = FA[d];
+        if (p.nc == 2) uF[(6 + d) * N + n] = FB[d];
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+__global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __restrict__ h,
+                                                    float* __restrict__ hn,
+                                                    const float* __restrict__ D,
+                                                    float* __restrict__ Dn,
+                                                    const float* __restrict__ uF,
+                                                    unsigned* __restrict__ flags) {
+    const int64_t n = node_id();
+    if (n >= p.N) return;
+    const int64_t N = p.N;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int x = (int)(n % nx);
+    const int64_t r = n / nx;
+    const int y = (int)(r % ny);
+    const int z = (int)(r / ny);
+
+    const float u[3] = {uF[n], uF[N + n], uF[2 * N + n]};
+    const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+
+    // densities of both components first (needed for phi and the local tau)
+    float dr[2] = {0.f, 0.f};
+    {
+        float jx = 0.f, jy = 0.f, jz = 0.f;
+        for (int s = 0; s < p.nc; ++s) pop_moments(h + (int64_t)s * kQ * N, N, n, dr[s], jx, jy, jz);
+    }
+    const float rA = p.rho0[0] + dr[0];
+    const float rB = p.nc == 2 ? p.rho0[1] + dr[1] : 0.0f;
+    float tau = p.tauA;
+    if (p.nc == 2) {
+        const float phi = (rA - rB) / (rA + rB);
+        const float fp = 0.5f * (1.0f + tanhf(phi * p.inv_delta));
+        tau = p.tauB + (p.tauA - p.tauB) * fp;
+    }
+    const float om = 1.0f / tau;
+    const float cf = 1.0f - 0.5f * om;
+
+    // destination row offsets (push streaming); -1 marks a link that leaves through a wall
+    const int xp = wrap1(x + 1, nx), xm = wrap1(x - 1, nx);
+    const int zp = wrap1(z + 1, nz), zm = wrap1(z - 1, nz);
+    float check = 0.0f;
+
+    for (int s = 0; s < p.nc; ++s) {
+        const float* hs = h + (int64_t)s * kQ * N;
+        float* hns = hn + (int64_t)s * kQ * N;
+        const float rs = s == 0 ? rA : rB;
+        const float drs = dr[s];
+        const float F[3] = {uF[(3 + 3 * s) * N + n], uF[(4 + 3 * s) * N + n], uF[(5 + 3 * s) * N + n]};
+        const float uFd = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) {
+            const float ha = hs[a * N + n];
+            const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
+            const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
+            const float heq = wgt(a) * (drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+            const float src = wgt(a) * (3.0f * (cF - uFd) + 9.0f * cu * cF);
+            const float post = ha - om * (ha - heq) + cf * src;
+            check += post;
+            const int yd = y + cy(a);
+            if (yd >= 0 && yd < ny) {
+                const int xd = cx(a) == 0 ? x : (cx(a) > 0 ? xp : xm);
+                const int zd = cz(a) == 0 ? z : (cz(a) > 0 ? zp : zm);
+                hns[a * N + ((int64_t)zd * ny + yd) * nx + xd] = post;
+            } else {
+                const float* uw = yd < 0 ? p.ub : p.ut;
+                const float cuw = cx(a) * uw[0] + cz(a) * uw[2];
+                hns[opp(a) * N + n] = post - 6.0f * wgt(a) * rs * cuw;
+            }
+        }
+    }
+
+    // ---- FENE-P step on C = I + D ----
+    float d0[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d0[k] = D[k * N + n];
+    float Gm[3][3];
+    float adv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        // neighbours along axis i
+        int64_t mp, mm;
+        float up[3], um[3];
+        if (i == 0) {
+            mp = ((int64_t)z * ny + y) * nx + xp;
+            mm = ((int64_t)z * ny + y) * nx + xm;
+        } else if (i == 2) {
+            mp = ((int64_t)zp * ny + y) * nx + x;
+            mm = ((int64_t)zm * ny + y) * nx + x;
+        } else {
+            // at a wall the ghost replaces the neighbour; keep the index in bounds anyway
+            mp = y == ny - 1 ? n : n + nx;
+            mm = y == 0 ? n : n - nx;
+        }
+        const bool top = (i == 1) && (y == ny - 1);
+        const bool bot = (i == 1) && (y == 0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            up[d] = top ? 2.0f * p.ut[d] - u[d] : uF[d * N + mp];
+            um[d] = bot ? 2.0f * p.ub[d] - u[d] : uF[d * N + mm];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Gm[i][d] = 0.5f * (up[d] - um[d]);
+        // first-order upwind difference of D along i
+        float dn[6];
+        if (u[i] >= 0.0f) {
+            if (bot) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = 2.0f * d0[k] - D[k * N + n + nx];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = D[k * N + mm];
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) adv[k] += u[i] * (d0[k] - dn[k]);
+        } else {
+            if (top) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = 2.0f * d0[k] - D[k * N + n - nx];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = D[k * N + mp];
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) adv[k] += u[i] * (dn[k] - d0[k]);
+        }
+    }
+    unsigned bad = 0u;
+    const float trd = d0[0] + d0[1] + d0[2];
+    const float den = p.L2m3 - trd;
+    if (!(den > 0.0f)) bad |= 2u;
+    const float inv = 1.0f / den;
+    const float f = p.L2m3 * inv;
+    const float fm1 = trd * inv;
+    float dnew[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            const int kk = sidx(a, b);
+            // (G^T C + C G)_ab with C = I + D
+            float st = Gm[b][a] + Gm[a][b];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) st += Gm[k][a] * d0[sidx(k, b)] + d0[sidx(a, k)] * Gm[k][b];
+            const float relax = (f * d0[kk] + (a == b ? fm1 : 0.0f)) * p.inv_tau_p;
+            dnew[kk] = d0[kk] + (-adv[kk] + st - relax);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        Dn[k * N + n] = dnew[k];
+        check += dnew[k];
+    }
+    // fault checks on the new state: non-finite, extensibility, leading minors of C
+    if (!isfinite(check)) bad |= 1u;
+    const float c0 = 1.0f + dnew[0], c1 = 1.0f + dnew[1], c2 = 1.0f + dnew[2];
+    if (!(c0 + c1 + c2 < p.L2)) bad |= 2u;
+    const float m2 = c0 * c1 - dnew[3] * dnew[3];
+    const float m3 = c0 * (c1 * c2 - dnew[5] * dnew[5]) - dnew[3] * (dnew[3] * c2 - dnew[5] * dnew[4]) +
+                     dnew[4] * (dnew[3] * dnew[5] - c1 * dnew[4]);
+    if (!(c0 > 0.0f && m2 > 0.0f && m3 > 0.0f)) bad |= 4u;
+    if (bad) atomicOr(flags, bad);
+}
+
+__global__ void k_clear_flags(unsigned* flags) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) flags[0] = 0u;
+}
+
+static inline dim3 grid_for(int64_t N) { return dim3((unsigned)((N + kBlock - 1) / kBlock)); }
+
+hipError_t launch_moments(const DevParams& p, const Buffers& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments, grid_for(p.N), dim3(kBlock), 0, s, p, b.h, b.mom);
+    return hipGetLastError();
+}
+hipError_t launch_forces(const DevParams& p, const Buffers& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_forces, grid_for(p.N), dim3(kBlock), 0, s, p, b.mom, b.D, b.uF, b.flags);
+    return hipGetLastError();
+}
+hipError_t launch_collide(const DevParams& p, const Buffers& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_collide, grid_for(p.N), dim3(kBlock), 0, s, p, b.h, b.hn, b.D, b.Dn, b.uF,
+                       b.flags);
+    return hipGetLastError();
+}
+hipError_t launch_clear_flags(const Buffers& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, b.flags);
+    return hipGetLastError();
+}
+
+}  // namespace lbfd

@@ -1,0 +1,62 @@
+// lbfd_internal.h -- device-side parameter block, buffer set and kernel launchers
+// shared by the host API translation units of liblbfd.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbfd {
+
+// Scalars every kernel needs, pre-converted to FP32 where the kernels compute in FP32.
+struct DevParams {
+    int nx, ny, nz, nc;
+    int64_t N;         // nx*ny*nz
+    float tauA, tauB;  // BGK times of the A-rich / B-rich phases
+    float G;           // Shan-Chen coupling
+    float inv_delta;   // 1/Delta of f+-(phi)
+    float rho0[2];     // storage shift per component
+    int phase;         // polymer phase (LBFD_POLYMER_*)
+    float pstress;     // eta_p/tau_p (0 when there is no feedback)
+    float inv_tau_p;   // 1/tau_p
+    float L2;          // L^2
+    float L2m3;        // L^2 - 3
+    float ub[3], ut[3];
+};
+
+// Views into the caller-owned device buffer.
+struct Buffers {
+    float* h;          // populations (f - w rho0) at time n: [nc][19][N]
+    float* hn;         // populations at n+1
+    float* D;          // C - I at time n: [6][N]
+    float* Dn;         // C - I at n+1
+    float* mom;        // side field: [nc+3][N] = delta rho_A, (delta rho_B), j_x, j_y, j_z
+    float* uF;         // side field: [3+3nc][N] = u (half-force), F_A, (F_B)
+    double* stage;     // FP64 staging for host transfers: 11 x stage_nodes
+    int64_t stage_nodes;
+    double* red;       // reduction partials
+    int64_t red_blocks;
+    double* red_out;   // final reduction record
+    unsigned* flags;   // fault bits (LBFD_FLAG_*), accumulated with atomicOr
+};
+
+// Sub-box of the lattice (global coordinates, x fastest in the flattened box).
+struct Box {
+    int x0, y0, z0, bx, by, bz;
+};
+
+constexpr int kDiagVals = 20;  // per-block FP64 reduction record length
+
+// kernels of one time step (k_step.hip)
+hipError_t launch_moments(const DevParams& p, const Buffers& b, hipStream_t s);
+hipError_t launch_forces(const DevParams& p, const Buffers& b, hipStream_t s);
+hipError_t launch_collide(const DevParams& p, const Buffers& b, hipStream_t s);
+hipError_t launch_clear_flags(const Buffers& b, hipStream_t s);
+
+// field transfer kernels (k_fields.hip)
+hipError_t launch_init_box(const DevParams& p, const Buffers& b, const Box& box, hipStream_t s);
+hipError_t launch_fields_box(const DevParams& p, const Buffers& b, const Box& box, hipStream_t s);
+
+// diagnostics (k_diag.hip): writes kDiagVals doubles to b.red_out
+hipError_t launch_diag(const DevParams& p, const Buffers& b, hipStream_t s);
+int64_t diag_blocks(int64_t N);
+
+}  // namespace lbfd

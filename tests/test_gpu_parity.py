@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs.  Tolerance: relative L2 <= 1e-5 on u and C (and rho), the accuracy
+target for FP32 populations and FP32 C; C - I is reported alongside.  Sizes span several
+blocks with ragged tails; the full 128x64x128 droplet grid is run directly."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+I6 = np.array([1, 1, 1, 0, 0, 0.0])[:, None]
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_1406_2686_amd
+
+    return paper_1406_2686_amd
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def run_both(lb, wl, steps):
+    lat = lb.from_workload(wl)
+    lat.step(steps)
+    g = lat.get_fields()
+    dg = lat.diagnostics()
+    o = oracle.from_workload(wl)
+    assert o.step(steps) == 0
+    r = o.get_fields()
+    do = o.diagnostics()
+    lat.close()
+    return g, r, dg, do
+
+
+def report(tag, g, r):
+    errs = {"u": rel(g[1], r[1]), "C": rel(g[2], r[2]), "C-I": rel(g[2] - I6, r[2] - I6),
+            "rho": rel(g[0], r[0]), "max|du|": float(np.max(np.abs(g[1] - r[1])))}
+    print(tag, " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    return errs
+
+
+def test_couette_fenep_16x32x16_4000_steps(lb):
+    """Single-component FENE-P plane Couette, 4000 steps (noise on C)."""
+    wl = workloads.couette_fenep()
+    g, r, dg, do = run_both(lb, wl, 4000)
+    e = report("couette4000", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-6
+    assert e["C-I"] < 1e-4
+    assert abs(dg["mass_A"] - do["mass_A"]) < 1e-6 * do["mass_A"]
+    # total momentum is ~0 by symmetry: bound the difference by the momentum scale N max|u|
+    scale = wl["rho"].size * do["max_u"]
+    assert abs(dg["mom_x"] - do["mom_x"]) < 1e-6 * scale
+
+
+@pytest.mark.parametrize("variant", ["as_written", "physics"])
+def test_droplet_128x64x128_full_grid(lb, variant):
+    """Two-component viscoelastic droplet on the full 128x64x128 grid, 100 steps."""
+    wl = workloads.droplet_cfg1(De=1.0, variant=variant)
+    g, r, dg, do = run_both(lb, wl, 100)
+    e = report(f"cfg1-{variant}", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    for k in ("mass_A", "mass_B"):
+        assert abs(dg[k] - do[k]) < 1e-6 * do[k]
+    assert abs(dg["D"] - do["D"]) < 1e-5 and abs(dg["xc"] - do["xc"]) < 1e-6 * do["xc"]
+
+
+@pytest.mark.parametrize("case", ["polyA", "polyB", "visc_ratio", "ragged"])
+def test_droplet_long_runs(lb, case):
+    """Smaller droplets over 1500 steps: polymer in droplet / matrix, viscosity ratio
+    (tau_A != tau_B), and a ragged odd-sized grid."""
+    G = workloads.G_PHYSICS_1_004
+    if case == "polyA":
+        wl = workloads.droplet_shear(nx=48, ny=24, nz=40, R=7.0, G=G, polymer_phase="A", De=1.0,
+                                     U=0.01)
+    elif case == "polyB":
+        wl = workloads.droplet_shear(nx=48, ny=24, nz=40, R=7.0, G=G, polymer_phase="B", L2=400.0,
+                                     De=1.0, U=0.01)
+    elif case == "visc_ratio":
+        wl = workloads.droplet_shear(nx=48, ny=24, nz=40, R=7.0, G=G, tau_A=1.4, tau_B=0.9,
+                                     polymer_phase="A", De=0.5, U=0.01)
+    else:
+        wl = workloads.droplet_shear(nx=37, ny=21, nz=29, R=6.0, G=G, polymer_phase="B", De=0.5,
+                                     U=0.008)
+    g, r, dg, do = run_both(lb, wl, 1500)
+    e = report(f"long-{case}", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert abs(dg["D"] - do["D"]) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 1), (5, 3, 2), (65, 7, 3), (3, 9, 70)])
+def test_degenerate_and_ragged_shapes(lb, shape):
+    """Minimal wall gap (ny = 3), single-node periodic directions and tails that do
+    not fill a 256-thread block."""
+    nx, ny, nz = shape
+    rho, u, C = workloads.random_state(nx, ny, nz, 2, seed=nx * 100 + nz, amp_rho=0.05,
+                                       amp_u=0.01, amp_C=0.1)
+    rho[0] += 0.5
+    wl = {"grid": {"nx": nx, "ny": ny, "nz": nz, "ncomp": 2},
+          "params": {"tau_A": 0.9, "tau_B": 1.1, "G": 1.2, "delta": 0.1, "rho0": [1.5, 1.0],
+                     "polymer_phase": "A", "eta_p": 0.1, "tau_p": 50.0, "L2": 60.0},
+          "walls": {"u_bottom": [-0.01, 0, 0.005], "u_top": [0.01, 0, -0.002]},
+          "rho": rho, "u": u, "C": C}
+    g, r, _, _ = run_both(lb, wl, 60)
+    e = report(f"shape{shape}", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+
+
+def test_zero_steps_returns_initial_fields(lb):
+    wl = workloads.droplet_shear(nx=20, ny=10, nz=12, R=3.0, G=2.0, polymer_phase="A", U=0.01)
+    g, r, _, _ = run_both(lb, wl, 0)
+    e = report("zero-steps", g, r)
+    assert e["u"] < 1e-6 and e["C"] < 1e-7 and e["rho"] < 1e-7
+
+
+def test_two_components_at_zero_coupling_match_one_component(lb):
+    nx, ny, nz = 24, 12, 10
+    rho1, u, C = workloads.random_state(nx, ny, nz, 1, seed=3, amp_rho=0.02, amp_u=0.01, amp_C=0.05)
+    share = np.random.default_rng(4).uniform(0.3, 0.7, rho1.shape[1])
+    rho2 = np.stack([rho1[0] * share, rho1[0] * (1 - share)])
+    base = {"tau_A": 0.8, "tau_B": 0.8, "G": 0.0, "delta": 0.1, "polymer_phase": "all",
+            "eta_p": 0.05, "tau_p": 40.0, "L2": 30.0}
+    walls = {"u_bottom": [-0.01, 0, 0], "u_top": [0.01, 0, 0]}
+    w1 = {"grid": {"nx": nx, "ny": ny, "nz": nz, "ncomp": 1}, "params": dict(base, rho0=[1.0, 0]),
+          "walls": walls, "rho": rho1, "u": u, "C": C}
+    w2 = {"grid": {"nx": nx, "ny": ny, "nz": nz, "ncomp": 2},
+          "params": dict(base, rho0=[0.5, 0.5]), "walls": walls, "rho": rho2, "u": u, "C": C}
+    l1 = lb.from_workload(w1)
+    l2 = lb.from_workload(w2)
+    l1.step(200)
+    l2.step(200)
+    a = l1.get_fields()
+    b = l2.get_fields()
+    assert rel(b[0].sum(0), a[0][0]) < 1e-6
+    assert rel(b[1], a[1]) < 1e-5 and rel(b[2], a[2]) < 1e-6
+
+
+def test_mass_conservation_and_determinism(lb):
+    """Per-component mass (FP64 reduction) drifts by less than 1e-6 relative over 2000
+    steps; repeated runs and a checkpoint split N + N reproduce 2N bitwise."""
+    wl = workloads.droplet_shear(nx=64, ny=32, nz=48, R=8.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="A", De=1.0, U=0.01)
+    lat = lb.from_workload(wl)
+    d0 = lat.diagnostics()
+    lat.step(1000)
+    blob = lat.get_state()
+    lat.step(1000)
+    d1 = lat.diagnostics()
+    f_a = lat.get_fields()
+    for k in ("mass_A", "mass_B"):
+        assert abs(d1[k] - d0[k]) < 1e-6 * d0[k]
+    lat2 = lb.from_workload(wl)
+    lat2.step(2000)
+    f_b = lat2.get_fields()
+    lat3 = lb.from_workload(wl)
+    lat3.set_state(blob)
+    lat3.step(1000)
+    f_c = lat3.get_fields()
+    for x, y, z in zip(f_a, f_b, f_c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    assert lat3.diagnostics()["step"] == 2000
+
+
+def test_fault_flags_and_argument_errors(lb):
+    wl = workloads.couette_fenep(nx=8, ny=8, nz=8)
+    lat = lb.from_workload(wl)
+    # host-side validation
+    with pytest.raises(lb.LbfdError) as ei:
+        lat.set_walls([0, 0.01, 0], [0, 0, 0])
+    assert ei.value.status == lb.EINVAL
+    bad = wl["C"].copy()
+    bad[0, 5] = np.nan
+    with pytest.raises(lb.LbfdError):
+        lat.set_fields(wl["rho"], wl["u"], bad)
+    bad = wl["C"].copy()
+    bad[0, 5] = 200.0
+    with pytest.raises(lb.LbfdError):
+        lat.set_fields(wl["rho"], wl["u"], bad)
+    with pytest.raises(lb.LbfdError):
+        lat.set_params(dict(wl["params"], tau_A=0.5))
+    # device-side detection, forced from the host with valid but extreme parameters:
+    # a relaxation time far below one step overshoots C through zero (not SPD)
+    C = wl["C"].copy()
+    C[0] += 0.2
+    lat.set_params(dict(wl["params"], tau_p=0.01))
+    lat.set_fields(wl["rho"], wl["u"], C)
+    st = lat.step_status(1)
+    assert st == lb.ENOTSPD
+    assert lat.diagnostics()["flags"] & lb.FLAG_NOT_SPD
+    # extensibility: a trace close to L^2 = 3.5 pushed over it by stretching
+    lat.set_params(dict(wl["params"], L2=3.5, tau_p=1e6))
+    C = wl["C"].copy()
+    C[3] = 0.3
+    lat.set_walls([-0.5, 0, 0], [0.5, 0, 0])
+    lat.set_fields(wl["rho"], wl["u"], C)
+    st = lat.step_status(50)
+    assert st in (lb.EEXTENSIBILITY, lb.ENOTSPD, lb.ENONFINITE)
+    assert lat.flags() & (lb.FLAG_EXTENSIBILITY | lb.FLAG_NOT_SPD | lb.FLAG_NONFINITE)
+    lat.close()
+    # stepping before fields are set is a state error
+    lat2 = lb.Lattice(8, 8, 8, 1, wl["params"])
+    assert lat2.step_status(1) == lb.ESTATE
