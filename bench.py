@@ -70,14 +70,39 @@ def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0):
                       f"({nodes} nodes, FP64, {el:.1f} s)"}
 
 
+def copy_probe(torch, gib, reps=20):
+    """Plain device-to-device copy of `gib` GiB: bytes moved = 2 x size per copy.  Gives
+    the achievable HBM bandwidth and, under rocprofv3 --pmc, the byte-counter scale."""
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    print(json.dumps({"copy_probe_GiB": gib, "bytes_per_copy": 2 * n * 4, "ms_per_copy": ms,
+                      "GB_per_s": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--grid", type=str, default="1024x256x1024")
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (HBM calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -89,6 +114,10 @@ def main():
 
     import paper_1406_2686_amd as lb
     import workloads
+
+    if args.copy_probe > 0:
+        copy_probe(torch, args.copy_probe)
+        return
 
     nx, ny, nz = (int(v) for v in args.grid.split("x"))
     N = nx * ny * nz
@@ -144,7 +173,7 @@ def main():
                    "diag_every": args.diag_every, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "one step (k_moments + k_forces + k_collide)",
+                     "kernel": "k_fused (the whole step, one launch per step)",
                      "alg_bytes_per_node": ALG_BYTES[2], "event_ms_per_step": round(step_ms, 4)},
         "checks": {"fault_flags": flags, "mass_drift_rel": mass_drift, "D_final": d1["D"]},
     }

@@ -150,6 +150,25 @@ lbfd_status lbfd_checkpoint_bytes(lbfd_ctx* ctx, uint64_t* bytes);
 lbfd_status lbfd_get_state(lbfd_ctx* ctx, void* host, uint64_t bytes);
 lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
 
+/* Launch shape of the step.  path: LBFD_PATH_FUSED (one pass over HBM per step, the
+ * default) or LBFD_PATH_SPLIT (three passes: moments, forces, collide; same arithmetic,
+ * kept as a cross-check).  tile: LBFD_TILE_32x8 / 32x16 / 16x16 (x by y nodes per
+ * workgroup of the fused pass; with two components 32x16 runs as 32x8).  zchunk: planes per workgroup along z, 0 = automatic.
+ * Results are identical for every tile and zchunk; only speed changes. */
+#define LBFD_PATH_FUSED 0
+#define LBFD_PATH_SPLIT 1
+#define LBFD_TILE_32x8 0
+#define LBFD_TILE_32x16 1
+#define LBFD_TILE_16x16 2
+typedef struct {
+    int32_t path;
+    int32_t tile;
+    int32_t zchunk;
+    int32_t reserved;
+} lbfd_tuning;
+lbfd_status lbfd_set_tuning(lbfd_ctx* ctx, const lbfd_tuning* t);
+lbfd_status lbfd_get_tuning(lbfd_ctx* ctx, lbfd_tuning* t);
+
 /* Library build/version string (static). */
 const char* lbfd_version(void);
 

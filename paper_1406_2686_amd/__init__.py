@@ -66,6 +66,14 @@ class Diag(ctypes.Structure):
                 "max_u": self.max_u, "flags": int(self.flags), "step": int(self.step)}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("zchunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+PATH_FUSED, PATH_SPLIT = 0, 1
+TILES = {"32x8": 0, "32x16": 1, "16x16": 2}
+
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _I32 = ctypes.c_int32
@@ -96,6 +104,8 @@ _sig("lbfd_diagnostics", [_P, ctypes.POINTER(Diag)])
 _sig("lbfd_checkpoint_bytes", [_P, ctypes.POINTER(ctypes.c_uint64)])
 _sig("lbfd_get_state", [_P, _P, ctypes.c_uint64])
 _sig("lbfd_set_state", [_P, _P, ctypes.c_uint64])
+_sig("lbfd_set_tuning", [_P, ctypes.POINTER(Tuning)])
+_sig("lbfd_get_tuning", [_P, ctypes.POINTER(Tuning)])
 _sig("lbfd_version", [], ctypes.c_char_p)
 _sig("lbfd_destroy", [_P], None)
 _sig("lbfd_last_error", [_P], ctypes.c_char_p)
@@ -235,6 +245,16 @@ class Lattice:
         self._check(_lib.lbfd_get_fields_box(self._h, x0, y0, z0, bx, by, bz, _dp(rho), _dp(u),
                                              _dp(C)))
         return rho, u, C
+
+    def set_tuning(self, path=PATH_FUSED, tile="32x8", zchunk=0):
+        t = Tuning(int(path), TILES[tile] if isinstance(tile, str) else int(tile), int(zchunk), 0)
+        self._check(_lib.lbfd_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(_lib.lbfd_get_tuning(self._h, ctypes.byref(t)))
+        inv = {v: k for k, v in TILES.items()}
+        return {"path": int(t.path), "tile": inv[int(t.tile)], "zchunk": int(t.zchunk)}
 
     def diagnostics(self) -> dict:
         d = Diag()

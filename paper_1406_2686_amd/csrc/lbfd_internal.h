@@ -43,6 +43,15 @@ struct Box {
     int x0, y0, z0, bx, by, bz;
 };
 
+// Launch shape of the fused step: tile 0 = 32x8, 1 = 32x16, 2 = 16x16 (x by y nodes per
+// workgroup); zchunk = planes per workgroup along z (0 = all).  path 0 = fused single
+// pass, 1 = three-pass split (moments, forces, collide).
+struct Tuning {
+    int path;
+    int tile;
+    int zchunk;
+};
+
 constexpr int kDiagVals = 20;  // per-block FP64 reduction record length
 
 // kernels of one time step (k_step.hip)
@@ -50,6 +59,8 @@ hipError_t launch_moments(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_forces(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_collide(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_clear_flags(const Buffers& b, hipStream_t s);
+// the fused single-pass step (k_fused.hip)
+hipError_t launch_fused(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
 
 // field transfer kernels (k_fields.hip)
 hipError_t launch_init_box(const DevParams& p, const Buffers& b, const Box& box, hipStream_t s);

@@ -211,3 +211,29 @@ def test_fault_flags_and_argument_errors(lb):
     # stepping before fields are set is a state error
     lat2 = lb.Lattice(8, 8, 8, 1, wl["params"])
     assert lat2.step_status(1) == lb.ESTATE
+
+
+def test_fused_launch_shapes_agree_bitwise_and_match_split_path(lb):
+    """Every tile shape and z-chunk of the fused single-pass step performs the same
+    per-node arithmetic, so results are bitwise identical; the three-pass split path
+    computes the same step in a different order (agreement to FP32 rounding)."""
+    wl = workloads.droplet_shear(nx=45, ny=19, nz=23, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="B", De=0.5, U=0.01)
+    ref = None
+    for tile, zc in [("32x8", 0), ("32x16", 5), ("16x16", 3), ("32x8", 1), ("32x8", 23)]:
+        lat = lb.from_workload(wl)
+        lat.set_tuning(lb.PATH_FUSED, tile, zc)
+        lat.step(40)
+        f = lat.get_fields()
+        lat.close()
+        if ref is None:
+            ref = f
+        else:
+            for a, b in zip(f, ref):
+                assert np.array_equal(a, b), (tile, zc)
+    lat = lb.from_workload(wl)
+    lat.set_tuning(lb.PATH_SPLIT)
+    lat.step(40)
+    s = lat.get_fields()
+    e = report("fused-vs-split", ref, s)
+    assert e["u"] < 2e-6 and e["C"] < 1e-7 and e["rho"] < 1e-7
