@@ -169,6 +169,57 @@ typedef struct {
 lbfd_status lbfd_set_tuning(lbfd_ctx* ctx, const lbfd_tuning* t);
 lbfd_status lbfd_get_tuning(lbfd_ctx* ctx, lbfd_tuning* t);
 
+/* Launch-shape autotuner (single lattice): times the fused step for every tile shape and a
+ * range of z-chunks on the current state, `reps` launches each, and keeps the fastest
+ * (also returned in *best with its time in *ms_per_step; either may be NULL).  The trial
+ * launches recompute the next time level from the current one without advancing, so the
+ * lattice state, step counter and fault flags are unchanged.  ESTATE before set_fields. */
+lbfd_status lbfd_autotune(lbfd_ctx* ctx, int32_t reps, lbfd_tuning* best, double* ms_per_step);
+
+/* ---------------------------------------------------------------------------------
+ * Batches: n independent lattices (same ncomp, any sizes) stepped together by one launch
+ * per step over a shared work table, replayed from a captured two-step hipGraph when the
+ * stream is not the null stream.  Used for parameter sweeps of droplets in shear.
+ * Device memory is one caller-owned buffer of lbfd_batch_state_bytes() bytes.
+ * --------------------------------------------------------------------------------- */
+typedef struct lbfd_batch lbfd_batch;
+
+/* Steady test: D (Sec. 4.1 deformation) is sampled every `every` steps (even); an instance
+ * is steady when |D(t) - D(t - window)| < tol (window a multiple of every). */
+typedef struct {
+    int32_t every;
+    int32_t window;
+    double tol;
+} lbfd_steady_crit;
+
+lbfd_status lbfd_batch_state_bytes(int32_t n, const lbfd_grid* grids, uint64_t* bytes);
+/* params: n entries; walls: n x 6 doubles (u_bottom[3], u_top[3]) per instance. */
+lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_params* params, const double* walls,
+                              void* dev_state, uint64_t bytes, void* hip_stream, lbfd_batch** out);
+/* Fields of instance i, as lbfd_set_fields. */
+lbfd_status lbfd_batch_set_fields(lbfd_batch* b, int32_t i, const double* rho, const double* u, const double* C);
+/* Fused path only; tile and zchunk as for a single lattice (zchunk >= 4 in a batch). */
+lbfd_status lbfd_batch_set_tuning(lbfd_batch* b, const lbfd_tuning* t);
+lbfd_status lbfd_batch_get_tuning(lbfd_batch* b, lbfd_tuning* t);
+/* Instances with active[i] == 0 are skipped by lbfd_batch_step (n bytes). */
+lbfd_status lbfd_batch_set_active(lbfd_batch* b, const uint8_t* active);
+/* Advance every active instance by nsteps; fault status as lbfd_step (any instance). */
+lbfd_status lbfd_batch_step(lbfd_batch* b, int64_t nsteps);
+/* Diagnostics of all n instances (out: n records). */
+lbfd_status lbfd_batch_diagnostics(lbfd_batch* b, lbfd_diag* out);
+lbfd_status lbfd_batch_get_fields(lbfd_batch* b, int32_t i, double* rho, double* u, double* C);
+/* Run all instances until each is steady (then retired from the launches) or max_steps.
+ * out: final diagnostics per instance; steady_step[i]: step at which instance i met the
+ * test, -1 if it did not.  Re-activates every instance before returning. */
+lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit, int64_t max_steps,
+                                     lbfd_diag* out, int64_t* steady_step);
+/* Launch-shape autotuner for the batch (state unchanged, as lbfd_autotune). */
+lbfd_status lbfd_batch_autotune(lbfd_batch* b, int32_t reps, lbfd_tuning* best, double* ms_per_step);
+/* The context of instance i (owned by the batch; valid until lbfd_batch_destroy). */
+lbfd_ctx* lbfd_batch_instance(lbfd_batch* b, int32_t i);
+void lbfd_batch_destroy(lbfd_batch* b);
+const char* lbfd_batch_last_error(const lbfd_batch* b);
+
 /* Library build/version string (static). */
 const char* lbfd_version(void);
 

@@ -106,6 +106,27 @@ _sig("lbfd_get_state", [_P, _P, ctypes.c_uint64])
 _sig("lbfd_set_state", [_P, _P, ctypes.c_uint64])
 _sig("lbfd_set_tuning", [_P, ctypes.POINTER(Tuning)])
 _sig("lbfd_get_tuning", [_P, ctypes.POINTER(Tuning)])
+class SteadyCrit(ctypes.Structure):
+    _fields_ = [("every", ctypes.c_int32), ("window", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+_sig("lbfd_autotune", [_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)])
+_sig("lbfd_batch_state_bytes", [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_uint64)])
+_sig("lbfd_batch_create", [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params), _D, _P,
+                           ctypes.c_uint64, _P, ctypes.POINTER(_P)])
+_sig("lbfd_batch_set_fields", [_P, ctypes.c_int32, _D, _D, _D])
+_sig("lbfd_batch_set_tuning", [_P, ctypes.POINTER(Tuning)])
+_sig("lbfd_batch_get_tuning", [_P, ctypes.POINTER(Tuning)])
+_sig("lbfd_batch_set_active", [_P, ctypes.POINTER(ctypes.c_uint8)])
+_sig("lbfd_batch_step", [_P, _I64])
+_sig("lbfd_batch_diagnostics", [_P, ctypes.POINTER(Diag)])
+_sig("lbfd_batch_get_fields", [_P, ctypes.c_int32, _D, _D, _D])
+_sig("lbfd_batch_run_to_steady", [_P, ctypes.POINTER(SteadyCrit), _I64, ctypes.POINTER(Diag),
+                                  ctypes.POINTER(ctypes.c_int64)])
+_sig("lbfd_batch_autotune", [_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)])
+_sig("lbfd_batch_instance", [_P, ctypes.c_int32], _P)
+_sig("lbfd_batch_destroy", [_P], None)
+_sig("lbfd_batch_last_error", [_P], ctypes.c_char_p)
 _sig("lbfd_version", [], ctypes.c_char_p)
 _sig("lbfd_destroy", [_P], None)
 _sig("lbfd_last_error", [_P], ctypes.c_char_p)
@@ -256,6 +277,16 @@ class Lattice:
         inv = {v: k for k, v in TILES.items()}
         return {"path": int(t.path), "tile": inv[int(t.tile)], "zchunk": int(t.zchunk)}
 
+    def autotune(self, reps: int = 3) -> dict:
+        """Time every launch shape on the current state (which is left unchanged) and keep
+        the fastest; returns the chosen shape and its ms per step."""
+        t = Tuning()
+        ms = ctypes.c_double(0)
+        self._check(_lib.lbfd_autotune(self._h, int(reps), ctypes.byref(t), ctypes.byref(ms)))
+        inv = {v: k for k, v in TILES.items()}
+        return {"path": int(t.path), "tile": inv[int(t.tile)], "zchunk": int(t.zchunk),
+                "ms_per_step": float(ms.value)}
+
     def diagnostics(self) -> dict:
         d = Diag()
         self._check(_lib.lbfd_diagnostics(self._h, ctypes.byref(d)))
@@ -280,3 +311,103 @@ def from_workload(wl, device="cuda") -> Lattice:
     lat.set_walls(wl["walls"]["u_bottom"], wl["walls"]["u_top"])
     lat.set_fields(wl["rho"], wl["u"], wl["C"])
     return lat
+
+
+class Batch:
+    """n independent lattices (same ncomp) stepped by one launch per step.  A dedicated
+    non-default torch stream is used so that the step graph can be captured."""
+
+    def __init__(self, workloads_list, device="cuda"):
+        import torch
+
+        self.n = len(workloads_list)
+        self.device = torch.device(device)
+        grids = (Grid * self.n)(*[Grid(w["grid"]["nx"], w["grid"]["ny"], w["grid"]["nz"],
+                                       w["grid"]["ncomp"]) for w in workloads_list])
+        params = (Params * self.n)(*[make_params(**w["params"]) for w in workloads_list])
+        walls = np.ascontiguousarray(
+            [list(w["walls"]["u_bottom"]) + list(w["walls"]["u_top"]) for w in workloads_list],
+            dtype=np.float64)
+        nb = ctypes.c_uint64(0)
+        st = _lib.lbfd_batch_state_bytes(self.n, grids, ctypes.byref(nb))
+        if st != OK:
+            raise LbfdError(st, "invalid batch grids")
+        self._buf = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._buf.data_ptr() + 255) // 256 * 256
+        self._stream = torch.cuda.Stream(device=self.device)
+        h = _P()
+        with torch.cuda.device(self.device):
+            st = _lib.lbfd_batch_create(self.n, grids, params, _dp(walls), _P(aligned), nb,
+                                        _P(self._stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise LbfdError(st, "lbfd_batch_create failed")
+        self._h = h
+        self.grids = [(g.nx, g.ny, g.nz, g.ncomp) for g in grids]
+        for i, w in enumerate(workloads_list):
+            self.set_fields(i, w["rho"], w["u"], w["C"])
+
+    def _check(self, st):
+        if st != OK:
+            raise LbfdError(st, _lib.lbfd_batch_last_error(self._h).decode())
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lbfd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_fields(self, i, rho, u, C):
+        nx, ny, nz, nc = self.grids[i]
+        N = nx * ny * nz
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(nc, N)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, N)
+        C = np.ascontiguousarray(C, dtype=np.float64).reshape(6, N)
+        self._check(_lib.lbfd_batch_set_fields(self._h, i, _dp(rho), _dp(u), _dp(C)))
+
+    def set_tuning(self, tile="32x8", zchunk=0):
+        t = Tuning(PATH_FUSED, TILES[tile] if isinstance(tile, str) else int(tile), int(zchunk), 0)
+        self._check(_lib.lbfd_batch_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, reps: int = 3) -> dict:
+        t = Tuning()
+        ms = ctypes.c_double(0)
+        self._check(_lib.lbfd_batch_autotune(self._h, int(reps), ctypes.byref(t), ctypes.byref(ms)))
+        inv = {v: k for k, v in TILES.items()}
+        return {"tile": inv[int(t.tile)], "zchunk": int(t.zchunk), "ms_per_step": float(ms.value)}
+
+    def set_active(self, active):
+        a = (ctypes.c_uint8 * self.n)(*[1 if x else 0 for x in active])
+        self._check(_lib.lbfd_batch_set_active(self._h, a))
+
+    def step(self, n: int):
+        self._check(_lib.lbfd_batch_step(self._h, int(n)))
+
+    def diagnostics(self):
+        d = (Diag * self.n)()
+        self._check(_lib.lbfd_batch_diagnostics(self._h, d))
+        return [x.to_dict() for x in d]
+
+    def get_fields(self, i):
+        nx, ny, nz, nc = self.grids[i]
+        N = nx * ny * nz
+        rho = np.zeros((nc, N))
+        u = np.zeros((3, N))
+        C = np.zeros((6, N))
+        self._check(_lib.lbfd_batch_get_fields(self._h, i, _dp(rho), _dp(u), _dp(C)))
+        return rho, u, C
+
+    def run_to_steady(self, every=100, window=1000, tol=1e-4, max_steps=100000):
+        crit = SteadyCrit(int(every), int(window), float(tol))
+        d = (Diag * self.n)()
+        ss = (ctypes.c_int64 * self.n)()
+        self._check(_lib.lbfd_batch_run_to_steady(self._h, ctypes.byref(crit), int(max_steps), d, ss))
+        return [x.to_dict() for x in d], [int(v) for v in ss]

@@ -268,27 +268,19 @@ __device__ __forceinline__ void phase_b(const DevParams& p, FusedTile<NC, TX, TY
     for (int d = 0; d < 3; ++d) L.u[sr][d][i1] = u[d];
 }
 
+// One workgroup's share of a step: tile [x0, x0+TX) x [y0, y0+TY), planes [z0, z1).
 template <int NC, int TX, int TY>
-__global__ __launch_bounds__(NC* TX* TY, (NC == 1 ? 2 : 1)) void k_fused(
-    DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
-    float* __restrict__ Dn, unsigned* __restrict__ flags, int zchunk) {
+__device__ __forceinline__ void fused_tile(const DevParams& p, const float* __restrict__ h,
+                                           float* __restrict__ hn, const float* __restrict__ D,
+                                           float* __restrict__ Dn, unsigned* __restrict__ flags,
+                                           FusedTile<NC, TX, TY>& L, int x0, int y0, int z0, int z1) {
     using T = FusedTile<NC, TX, TY>;
     static_assert(T::NH2 <= T::NT, "one R2 halo node per thread at most");
     static_assert(T::A1 <= 2 * T::NTH, "phase B covers the R1 region in two passes at most");
-    __shared__ T L;
 
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const int64_t N = p.N;
     const int64_t plane = (int64_t)nx * ny;
-    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
-    const int64_t bid = xcd_remap_f(blockIdx.x, gridDim.x);
-    const int tx_i = (int)(bid % ntx);
-    const int64_t rem = bid / ntx;
-    const int ty_i = (int)(rem % nty);
-    const int zc_i = (int)(rem / nty);
-    const int x0 = tx_i * TX, y0 = ty_i * TY;
-    const int z0 = zc_i * zchunk;
-    const int z1 = min(z0 + zchunk, nz);
 
     const int tid = threadIdx.x;
     const int comp = tid / T::NT;   // component this thread loads and collides
@@ -536,6 +528,37 @@ __global__ __launch_bounds__(NC* TX* TY, (NC == 1 ? 2 : 1)) void k_fused(
 }
 
 template <int NC, int TX, int TY>
+__global__ __launch_bounds__(NC* TX* TY, (NC == 1 ? 2 : 1)) void k_fused(
+    DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
+    float* __restrict__ Dn, unsigned* __restrict__ flags, int zchunk) {
+    __shared__ FusedTile<NC, TX, TY> L;
+    const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
+    const int64_t bid = xcd_remap_f(blockIdx.x, gridDim.x);
+    const int tx_i = (int)(bid % ntx);
+    const int64_t rem = bid / ntx;
+    const int ty_i = (int)(rem % nty);
+    const int zc_i = (int)(rem / nty);
+    const int z0 = zc_i * zchunk;
+    fused_tile<NC, TX, TY>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0, min(z0 + zchunk, p.nz));
+}
+
+// Many independent lattices in one launch: each workgroup takes one entry of the work
+// table (instance, tile, z range) and steps that part of its instance.  The instance's
+// buffer holding time level n is cur ^ parity, so a two-launch graph (parity 0, 1)
+// replays any even number of steps.
+template <int NC, int TX, int TY>
+__global__ __launch_bounds__(NC* TX* TY, (NC == 1 ? 2 : 1)) void k_fused_batch(
+    const BatchInstance* __restrict__ inst, const WorkItem* __restrict__ work, int parity) {
+    __shared__ FusedTile<NC, TX, TY> L;
+    const int64_t bid = xcd_remap_f(blockIdx.x, gridDim.x);
+    const WorkItem w = work[bid];
+    const BatchInstance& bi = inst[w.inst];
+    const DevParams p = bi.p;
+    const int c = bi.cur ^ parity;
+    fused_tile<NC, TX, TY>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0, w.z0, w.z1);
+}
+
+template <int NC, int TX, int TY>
 static hipError_t launch_fused_t(const DevParams& p, const Buffers& b, int zchunk, hipStream_t s) {
     const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
     const int nzc = (p.nz + zchunk - 1) / zchunk;
@@ -543,6 +566,32 @@ static hipError_t launch_fused_t(const DevParams& p, const Buffers& b, int zchun
     hipLaunchKernelGGL((k_fused<NC, TX, TY>), dim3((unsigned)nblk), dim3(NC * TX * TY), 0, s, p, b.h, b.hn, b.D,
                        b.Dn, b.flags, zchunk);
     return hipGetLastError();
+}
+
+hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,
+                              int parity, hipStream_t s) {
+    if (nwork <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nwork);
+    if (ncomp == 2) {
+        if (tile == 2)
+            hipLaunchKernelGGL((k_fused_batch<2, 16, 16>), grid, dim3(512), 0, s, inst, work, parity);
+        else
+            hipLaunchKernelGGL((k_fused_batch<2, 32, 8>), grid, dim3(512), 0, s, inst, work, parity);
+    } else {
+        if (tile == 1)
+            hipLaunchKernelGGL((k_fused_batch<1, 32, 16>), grid, dim3(512), 0, s, inst, work, parity);
+        else if (tile == 2)
+            hipLaunchKernelGGL((k_fused_batch<1, 16, 16>), grid, dim3(256), 0, s, inst, work, parity);
+        else
+            hipLaunchKernelGGL((k_fused_batch<1, 32, 8>), grid, dim3(256), 0, s, inst, work, parity);
+    }
+    return hipGetLastError();
+}
+
+// tile extent of a tuning choice (two components run the 32x16 choice as 32x8)
+void fused_tile_shape(int ncomp, int tile, int* tx, int* ty) {
+    *tx = tile == 2 ? 16 : 32;
+    *ty = tile == 2 ? 16 : ((tile == 1 && ncomp == 1) ? 16 : 8);
 }
 
 hipError_t launch_fused(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s) {

@@ -360,6 +360,10 @@ __global__ void k_clear_flags(unsigned* flags) {
     if (threadIdx.x == 0 && blockIdx.x == 0) flags[0] = 0u;
 }
 
+__global__ void k_set_flags(unsigned* flags, unsigned v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) flags[0] = v;
+}
+
 static inline dim3 grid_for(int64_t N) { return dim3((unsigned)((N + kBlock - 1) / kBlock)); }
 
 hipError_t launch_moments(const DevParams& p, const Buffers& b, hipStream_t s) {
@@ -373,6 +377,10 @@ hipError_t launch_forces(const DevParams& p, const Buffers& b, hipStream_t s) {
 hipError_t launch_collide(const DevParams& p, const Buffers& b, hipStream_t s) {
     hipLaunchKernelGGL(k_collide, grid_for(p.N), dim3(kBlock), 0, s, p, b.h, b.hn, b.D, b.Dn, b.uF,
                        b.flags);
+    return hipGetLastError();
+}
+hipError_t launch_set_flags(const Buffers& b, unsigned v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_flags, dim3(1), dim3(64), 0, s, b.flags, v);
     return hipGetLastError();
 }
 hipError_t launch_clear_flags(const Buffers& b, hipStream_t s) {

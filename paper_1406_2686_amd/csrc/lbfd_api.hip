@@ -11,29 +11,10 @@
 #include <vector>
 
 #include "lbfd.h"
+#include "lbfd_ctx.h"
 #include "lbfd_internal.h"
 
 using namespace lbfd;
-
-struct lbfd_ctx {
-    lbfd_grid grid;
-    lbfd_params params;
-    double ub[3], ut[3];
-    DevParams dp;
-    Buffers buf;
-    Tuning tune;
-    float* hbuf[2];
-    float* Dbuf[2];
-    int cur;
-    hipStream_t stream;
-    int device;
-    char* dev;
-    uint64_t bytes;
-    int64_t steps;
-    unsigned flags_seen;
-    bool have_fields;
-    std::string err;
-};
 
 namespace {
 
@@ -121,12 +102,6 @@ void fill_devparams(lbfd_ctx* c) {
     }
 }
 
-void bind_current(lbfd_ctx* c) {
-    c->buf.h = c->hbuf[c->cur];
-    c->buf.hn = c->hbuf[1 - c->cur];
-    c->buf.D = c->Dbuf[c->cur];
-    c->buf.Dn = c->Dbuf[1 - c->cur];
-}
 
 lbfd_status fail(lbfd_ctx* c, lbfd_status st, const std::string& msg) {
     if (c) c->err = msg;
@@ -153,6 +128,17 @@ lbfd_status flags_status(unsigned f) {
 bool box_ok(const lbfd_ctx* c, int x0, int y0, int z0, int bx, int by, int bz) {
     return x0 >= 0 && y0 >= 0 && z0 >= 0 && bx >= 1 && by >= 1 && bz >= 1 && x0 + bx <= c->grid.nx &&
            y0 + by <= c->grid.ny && z0 + bz <= c->grid.nz;
+}
+
+}  // namespace
+
+namespace lbfd {
+
+void bind_current(lbfd_ctx* c) {
+    c->buf.h = c->hbuf[c->cur];
+    c->buf.hn = c->hbuf[1 - c->cur];
+    c->buf.D = c->Dbuf[c->cur];
+    c->buf.Dn = c->Dbuf[1 - c->cur];
 }
 
 // derived side fields (moments, forces, half-force velocity) of the current state
@@ -202,6 +188,10 @@ hipError_t read_flags(lbfd_ctx* c, unsigned* out) {
     *out = f;
     return e;
 }
+
+}  // namespace lbfd
+
+namespace {
 
 // Checks of one box of host fields before upload (finite, positive densities, C SPD with tr C < L^2).
 const char* fields_problem(const lbfd_ctx* c, int64_t B, const double* rho, const double* u, const double* C) {

@@ -1,0 +1,37 @@
+// lbfd_ctx.h -- the lattice context shared by the single-lattice and batched host code
+// of liblbfd.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "lbfd.h"
+#include "lbfd_internal.h"
+
+struct lbfd_ctx {
+    lbfd_grid grid;
+    lbfd_params params;
+    double ub[3], ut[3];
+    lbfd::DevParams dp;
+    lbfd::Buffers buf;
+    lbfd::Tuning tune;
+    float* hbuf[2];
+    float* Dbuf[2];
+    int cur;
+    hipStream_t stream;
+    int device;
+    char* dev;
+    uint64_t bytes;
+    int64_t steps;
+    unsigned flags_seen;
+    bool have_fields;
+    std::string err;
+};
+
+namespace lbfd {
+hipError_t compute_side_fields(lbfd_ctx* c);
+int auto_zchunk(const lbfd_grid& g, int tile);
+hipError_t enqueue_steps(lbfd_ctx* c, int64_t n);
+hipError_t read_flags(lbfd_ctx* c, unsigned* out);
+void bind_current(lbfd_ctx* c);
+}  // namespace lbfd

@@ -54,13 +54,32 @@ struct Tuning {
 
 constexpr int kDiagVals = 20;  // per-block FP64 reduction record length
 
+// One lattice of a batch, as the batched step kernel sees it (device memory).
+struct BatchInstance {
+    DevParams p;
+    float* h[2];       // the two population buffers
+    float* D[2];       // the two C - I buffers
+    unsigned* flags;   // this instance's fault bits
+    int cur;           // buffer index holding time level n when the launch parity is 0
+    int pad;
+};
+
+// One workgroup of a batched step: instance, tile origin, z range [z0, z1).
+struct WorkItem {
+    int inst, x0, y0, z0, z1, pad0, pad1, pad2;
+};
+
 // kernels of one time step (k_step.hip)
 hipError_t launch_moments(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_forces(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_collide(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_clear_flags(const Buffers& b, hipStream_t s);
+hipError_t launch_set_flags(const Buffers& b, unsigned v, hipStream_t s);
 // the fused single-pass step (k_fused.hip)
 hipError_t launch_fused(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
+hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,
+                              int parity, hipStream_t s);
+void fused_tile_shape(int ncomp, int tile, int* tx, int* ty);
 
 // field transfer kernels (k_fields.hip)
 hipError_t launch_init_box(const DevParams& p, const Buffers& b, const Box& box, hipStream_t s);

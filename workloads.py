@@ -202,3 +202,38 @@ def random_state(nx, ny, nz, ncomp, seed, amp_rho=0.05, amp_u=0.02, amp_C=0.2):
     C[4] = S[:, 0, 2]
     C[5] = S[:, 1, 2]
     return rho, u, C
+
+
+def sweep_cases(n=64, seed=3, sigma=None, G=None):
+    """Droplet-in-shear sweep instances drawn with numpy.random.default_rng(seed):
+    N_x = N_z in {64, 128, 192}, N_y in {32, 48, 64}, R ~ U{8..24} subject to 2R/H <= 0.75
+    and 4R <= N_x, Ca ~ U[0.05, 0.4], De ~ logU[0.1, 2], viscosity ratio lambda ~
+    logU[0.5, 2] (tau_A = 1/2 + lambda (tau_B - 1/2), tau_B = 1), L^2 in {50, 100, 400}, and
+    the polymer in the droplet or the matrix by a coin flip."""
+    rng = np.random.default_rng(seed)
+    cases = []
+    while len(cases) < n:
+        nxz = int(rng.choice([64, 128, 192]))
+        ny = int(rng.choice([32, 48, 64]))
+        R = int(rng.integers(8, 25))
+        Ca = float(rng.uniform(0.05, 0.4))
+        De = float(np.exp(rng.uniform(np.log(0.1), np.log(2.0))))
+        lam = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
+        L2 = float(rng.choice([50.0, 100.0, 400.0]))
+        phase = "A" if rng.uniform() < 0.5 else "B"
+        if 2 * R / ny > 0.75 or 4 * R > nxz:
+            continue
+        cases.append({"nx": nxz, "ny": ny, "nz": nxz, "R": float(R), "Ca": Ca, "De": De,
+                      "lam": lam, "L2": L2, "polymer_phase": phase})
+    return cases
+
+
+def sweep_workload(case, sigma=None, G=None, **kw):
+    """Workload dict for one sweep case (see sweep_cases)."""
+    tau_B = 1.0
+    tau_A = 0.5 + case["lam"] * (tau_B - 0.5)
+    return droplet_shear(nx=case["nx"], ny=case["ny"], nz=case["nz"], R=case["R"],
+                         G=G if G is not None else G_PHYSICS_1_004, tau_A=tau_A, tau_B=tau_B,
+                         polymer_phase=case["polymer_phase"], L2=case["L2"], De=case["De"],
+                         Ca=case["Ca"], sigma=sigma, name=f"sweep_{case['nx']}x{case['ny']}",
+                         **kw)
