@@ -220,6 +220,56 @@ lbfd_ctx* lbfd_batch_instance(lbfd_batch* b, int32_t i);
 void lbfd_batch_destroy(lbfd_batch* b);
 const char* lbfd_batch_last_error(const lbfd_batch* b);
 
+/* ---------------------------------------------------------------------------------
+ * Surrogate network for droplet sweeps: an MLP 5 -> 128 -> 128 -> 3 with GELU
+ * (GELU(z) = z (1 + erf(z / sqrt 2)) / 2) mapping (Ca, De, viscosity ratio, 2R/H, log L^2),
+ * standardised by the caller, to standardised (D, theta, warm-start C amplitude).  Training
+ * in FP32 on the device (mean-squared-error loss, Adam), inference in BF16 with FP32
+ * accumulation on the matrix cores.  The lattice solver stays the reference: the network
+ * only proposes warm starts and its error is judged against solver runs.
+ * Parameter vector (FP32, LBFD_MLP_NPARAMS values in this order): W1[128][5], b1[128],
+ * W2[128][128], b2[128], W3[3][128], b3[3]; row-major, y = W x + b.
+ * All X / T / Y arrays here are host arrays, row-major [sample][feature].
+ * --------------------------------------------------------------------------------- */
+#define LBFD_MLP_IN 5
+#define LBFD_MLP_HIDDEN 128
+#define LBFD_MLP_OUT 3
+#define LBFD_MLP_NPARAMS 17667
+
+typedef struct lbfd_mlp lbfd_mlp;
+typedef struct {
+    int32_t epochs;  /* passes over the training set                        */
+    int32_t batch;   /* minibatch size (<= max_batch)                        */
+    float lr;        /* Adam step size                                       */
+    float beta1, beta2, eps;
+    uint64_t seed;   /* shuffling seed                                       */
+} lbfd_train_opts;
+
+/* Device bytes for a network with minibatches up to max_batch samples and a resident
+ * training set of up to max_train samples. */
+lbfd_status lbfd_mlp_state_bytes(int32_t max_batch, int32_t max_train, uint64_t* bytes);
+/* Create in a caller-owned device buffer; weights Glorot-uniform from `seed`, biases 0. */
+lbfd_status lbfd_mlp_create(int32_t max_batch, int32_t max_train, uint64_t seed, void* dev_state, uint64_t bytes,
+                            void* hip_stream, lbfd_mlp** out);
+/* Replace / read the LBFD_MLP_NPARAMS parameters (set also resets the Adam moments). */
+lbfd_status lbfd_mlp_set_params(lbfd_mlp* m, const float* params);
+lbfd_status lbfd_mlp_get_params(lbfd_mlp* m, float* params);
+/* FP32 forward pass, n samples (chunked by max_batch). */
+lbfd_status lbfd_mlp_forward(lbfd_mlp* m, const float* X, int32_t n, float* Y);
+/* Mean-squared-error loss over n x 3 outputs (n <= max_batch) and its gradient with respect
+ * to every parameter (grad: LBFD_MLP_NPARAMS floats, may be NULL; loss may be NULL). */
+lbfd_status lbfd_mlp_loss_grad(lbfd_mlp* m, const float* X, const float* T, int32_t n, float* loss, float* grad);
+/* One Adam update with the gradient of the last lbfd_mlp_loss_grad (bias-corrected). */
+lbfd_status lbfd_mlp_adam_step(lbfd_mlp* m, const lbfd_train_opts* opts);
+/* Minibatch Adam training on the device over n samples (n <= max_train); returns the loss
+ * of the last minibatch. */
+lbfd_status lbfd_mlp_train(lbfd_mlp* m, const float* X, const float* T, int32_t n, const lbfd_train_opts* opts,
+                           float* final_loss);
+/* BF16 inference (weights rounded to BF16 once after each update). */
+lbfd_status lbfd_mlp_infer_bf16(lbfd_mlp* m, const float* X, int32_t n, float* Y);
+void lbfd_mlp_destroy(lbfd_mlp* m);
+const char* lbfd_mlp_last_error(const lbfd_mlp* m);
+
 /* Library build/version string (static). */
 const char* lbfd_version(void);
 

@@ -127,6 +127,25 @@ _sig("lbfd_batch_autotune", [_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.
 _sig("lbfd_batch_instance", [_P, ctypes.c_int32], _P)
 _sig("lbfd_batch_destroy", [_P], None)
 _sig("lbfd_batch_last_error", [_P], ctypes.c_char_p)
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+_F = ctypes.POINTER(ctypes.c_float)
+_sig("lbfd_mlp_state_bytes", [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)])
+_sig("lbfd_mlp_create", [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _P, ctypes.c_uint64, _P,
+                         ctypes.POINTER(_P)])
+_sig("lbfd_mlp_set_params", [_P, _F])
+_sig("lbfd_mlp_get_params", [_P, _F])
+_sig("lbfd_mlp_forward", [_P, _F, ctypes.c_int32, _F])
+_sig("lbfd_mlp_loss_grad", [_P, _F, _F, ctypes.c_int32, _F, _F])
+_sig("lbfd_mlp_adam_step", [_P, ctypes.POINTER(TrainOpts)])
+_sig("lbfd_mlp_train", [_P, _F, _F, ctypes.c_int32, ctypes.POINTER(TrainOpts), _F])
+_sig("lbfd_mlp_infer_bf16", [_P, _F, ctypes.c_int32, _F])
+_sig("lbfd_mlp_destroy", [_P], None)
+_sig("lbfd_mlp_last_error", [_P], ctypes.c_char_p)
 _sig("lbfd_version", [], ctypes.c_char_p)
 _sig("lbfd_destroy", [_P], None)
 _sig("lbfd_last_error", [_P], ctypes.c_char_p)
@@ -411,3 +430,92 @@ class Batch:
         ss = (ctypes.c_int64 * self.n)()
         self._check(_lib.lbfd_batch_run_to_steady(self._h, ctypes.byref(crit), int(max_steps), d, ss))
         return [x.to_dict() for x in d], [int(v) for v in ss]
+
+
+MLP_NPARAMS = 17667
+
+
+def _fp(a):
+    assert a.dtype == np.float32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_F)
+
+
+class MLP:
+    """The 5 -> 128 -> 128 -> 3 GELU surrogate on the GPU (training FP32, inference BF16)."""
+
+    def __init__(self, max_batch=512, max_train=4096, seed=0, device="cuda"):
+        import torch
+
+        nb = ctypes.c_uint64(0)
+        st = _lib.lbfd_mlp_state_bytes(int(max_batch), int(max_train), ctypes.byref(nb))
+        if st != OK:
+            raise LbfdError(st, "lbfd_mlp_state_bytes")
+        self.device = torch.device(device)
+        self._buf = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._buf.data_ptr() + 255) // 256 * 256
+        self._stream = torch.cuda.current_stream(self.device)
+        h = _P()
+        with torch.cuda.device(self.device):
+            st = _lib.lbfd_mlp_create(int(max_batch), int(max_train), ctypes.c_uint64(seed), _P(aligned),
+                                      nb, _P(self._stream.cuda_stream), ctypes.byref(h))
+        if st != OK:
+            raise LbfdError(st, "lbfd_mlp_create")
+        self._h = h
+        self.max_batch = int(max_batch)
+
+    def _check(self, st):
+        if st != OK:
+            raise LbfdError(st, _lib.lbfd_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lbfd_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == MLP_NPARAMS
+        self._check(_lib.lbfd_mlp_set_params(self._h, _fp(p)))
+
+    def get_params(self):
+        p = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        self._check(_lib.lbfd_mlp_get_params(self._h, _fp(p)))
+        return p
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.zeros((X.shape[0], 3), dtype=np.float32)
+        self._check(_lib.lbfd_mlp_forward(self._h, _fp(X), X.shape[0], _fp(Y)))
+        return Y
+
+    def infer_bf16(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.zeros((X.shape[0], 3), dtype=np.float32)
+        self._check(_lib.lbfd_mlp_infer_bf16(self._h, _fp(X), X.shape[0], _fp(Y)))
+        return Y
+
+    def loss_grad(self, X, T):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        g = np.zeros(MLP_NPARAMS, dtype=np.float32)
+        self._check(_lib.lbfd_mlp_loss_grad(self._h, _fp(X), _fp(T), X.shape[0], _fp(loss), _fp(g)))
+        return float(loss[0]), g
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        o = TrainOpts(1, 1, lr, beta1, beta2, eps, 0)
+        self._check(_lib.lbfd_mlp_adam_step(self._h, ctypes.byref(o)))
+
+    def train(self, X, T, epochs=200, batch=256, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        o = TrainOpts(int(epochs), int(batch), lr, beta1, beta2, eps, int(seed))
+        loss = np.zeros(1, dtype=np.float32)
+        self._check(_lib.lbfd_mlp_train(self._h, _fp(X), _fp(T), X.shape[0], ctypes.byref(o), _fp(loss)))
+        return float(loss[0])
