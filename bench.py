@@ -93,6 +93,61 @@ def copy_probe(torch, gib, reps=20):
           flush=True)
 
 
+def sweep(lb, workloads, args):
+    """Time to steady D for a held-out set of droplet-in-shear cases: plain per-case solves
+    (cold start, one lattice at a time) vs one batched solve (cold) vs one batched solve
+    warm-started from the surrogate trained on batched solves of the training cases."""
+    import numpy as np
+
+    from paper_1406_2686_amd import surrogate as sg
+
+    crit = dict(every=100, window=1000, tol=1e-4, max_steps=args.max_steps)
+    train = workloads.sweep_cases(args.n_train, seed=4001, scale=args.scale)
+    test = workloads.sweep_cases(args.n_test, seed=10001, scale=args.scale)
+    wtrain = [workloads.sweep_workload(c) for c in train]
+    wtest = [workloads.sweep_workload(c) for c in test]
+    log(f"sweep: {len(train)} training / {len(test)} held-out cases, scale {args.scale}")
+    gen = sg.solve(lb, wtrain, **crit)
+    ok = gen["steady_step"] > 0
+    log(f"training data: {ok.sum()} steady of {len(train)} in {gen['wall_s']:.1f} s")
+    X = sg.features(train)[ok]
+    Y = np.stack([gen["D"], gen["theta"], gen["amp"]], 1)[ok]
+    model = sg.Surrogate(lb, seed=1, max_train=max(4096, len(train)))
+    t0 = time.perf_counter()
+    loss = model.fit(X, Y, epochs=400, batch=128, lr=2e-3, seed=2)
+    t_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pred = model.predict(sg.features(test))
+    t_pred = time.perf_counter() - t0
+    plain = sg.solve_plain(lb, wtest, **crit)
+    log(f"plain sweep: {plain['wall_s']:.1f} s")
+    cold = sg.solve(lb, wtest, **crit)
+    log(f"batched cold sweep: {cold['wall_s']:.1f} s")
+    warm = sg.solve(lb, wtest, warm=[tuple(r) for r in pred], **crit)
+    log(f"batched warm sweep: {warm['wall_s']:.1f} s")
+    judge = plain["D"]
+    valid = plain["steady_step"] > 0
+    err_pred = np.abs(pred[:, 0] - judge)[valid]
+    err_warm = np.abs(warm["D"] - judge)[valid]
+    out = {"metric": "sweep time-to-steady-D (|dD| <= 0.01 against plain solves)", "unit": "s",
+           "value": round(warm["wall_s"] + t_pred, 2), "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic", "dtype": "f32 solver, bf16 surrogate inference",
+           "config": {"workload": f"droplet sweep, grids x{args.scale} of 64-192 x 32-64",
+                      "n_train": len(train), "n_test": len(test), **crit},
+           "plain_per_case_s": round(plain["wall_s"], 2), "batched_cold_s": round(cold["wall_s"], 2),
+           "batched_warm_s": round(warm["wall_s"], 2), "surrogate_infer_s": round(t_pred, 4),
+           "training_data_s": round(gen["wall_s"], 2), "train_s": round(t_train, 2), "final_loss": loss,
+           "surrogate_within_0.01": float(np.mean(err_pred <= 0.01)),
+           "surrogate_mean_abs_dD": float(err_pred.mean()),
+           "warm_within_0.01": float(np.mean(err_warm <= 0.01)),
+           "steps_cold_mean": float(cold["steady_step"][cold["steady_step"] > 0].mean()),
+           "steps_warm_mean": float(warm["steady_step"][warm["steady_step"] > 0].mean()),
+           "unsteady_or_fault": {"plain": int((plain["steady_step"] <= 0).sum()),
+                                 "cold": int((cold["steady_step"] <= 0).sum()),
+                                 "warm": int((warm["steady_step"] <= 0).sum())}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +156,12 @@ def main():
     ap.add_argument("--grid", type=str, default="1024x256x1024")
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="droplet-sweep mode: plain vs batched vs surrogate-warm-started time to steady D")
+    ap.add_argument("--n-train", type=int, default=2048)
+    ap.add_argument("--n-test", type=int, default=256)
+    ap.add_argument("--scale", type=float, default=0.5)
+    ap.add_argument("--max-steps", type=int, default=12000)
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM calibration)")
     args = ap.parse_args()
@@ -117,6 +178,9 @@ def main():
 
     if args.copy_probe > 0:
         copy_probe(torch, args.copy_probe)
+        return
+    if args.sweep:
+        sweep(lb, workloads, args)
         return
 
     nx, ny, nz = (int(v) for v in args.grid.split("x"))

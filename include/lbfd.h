@@ -90,6 +90,8 @@ typedef struct {
     uint32_t flags;         /* LBFD_FLAG_* seen since the last lbfd_set_fields         */
     uint32_t reserved;
     int64_t step;           /* steps taken since lbfd_set_fields                       */
+    double poly_trace_excess; /* mean of tr C - 3 over the polymer phase, weighted by the
+                               * feedback modulation m(phi); 0 without a polymer phase */
 } lbfd_diag;
 
 /* Device bytes needed for a grid (populations x2, C x2, side fields, staging, scratch).
@@ -210,7 +212,8 @@ lbfd_status lbfd_batch_diagnostics(lbfd_batch* b, lbfd_diag* out);
 lbfd_status lbfd_batch_get_fields(lbfd_batch* b, int32_t i, double* rho, double* u, double* C);
 /* Run all instances until each is steady (then retired from the launches) or max_steps.
  * out: final diagnostics per instance; steady_step[i]: step at which instance i met the
- * test, -1 if it did not.  Re-activates every instance before returning. */
+ * test, -1 if it did not, -2 if it raised a fault flag (it is then retired and its flags
+ * are in out[i].flags).  Re-activates every instance before returning. */
 lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit, int64_t max_steps,
                                      lbfd_diag* out, int64_t* steady_step);
 /* Launch-shape autotuner for the batch (state unchanged, as lbfd_autotune). */

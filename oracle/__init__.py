@@ -6,7 +6,7 @@ anything here, and nothing here imports the product package.
 
 ``lbfd_oracle.c`` holds the stepping algorithm (stages S1-S11 in the paper's order);
 this module is ctypes marshalling plus the paper's closed forms used as pins
-(``closed_forms.py``).
+(``tests/paper_closed_forms.py``).
 """
 from __future__ import annotations
 
@@ -26,7 +26,7 @@ FLAG_NONFINITE, FLAG_EXTENSIBILITY, FLAG_NOT_SPD = 1, 2, 4
 DIAG_FIELDS = (
     "mass_A", "mass_B", "mom_x", "mom_y", "mom_z", "W", "xc", "yc", "zc",
     "Mxx", "Myy", "Mzz", "Mxy", "Mxz", "Myz", "D", "theta_deg",
-    "min_L2_minus_trC", "min_minor", "max_u", "flags",
+    "min_L2_minus_trC", "min_minor", "max_u", "flags", "poly_trace_excess",
 )
 
 
@@ -193,7 +193,7 @@ class Oracle:
         return f
 
     def diagnostics(self) -> dict:
-        out = np.zeros(21)
+        out = np.zeros(22)
         lib().orc_diagnostics(self._h, _dp(out))
         return dict(zip(DIAG_FIELDS, out.tolist()))
 

@@ -525,7 +525,8 @@ void orc_get_pops(const orc_t *o, double *f) { memcpy(f, o->f, sizeof(double) * 
  *  [0..1] mass per species, [2..4] total momentum sum rho u, [5] W = sum w with
  *  w = max(phi, 0), [6..8] centroid, [9..14] second moments about the centroid
  *  (xx, yy, zz, xy, xz, yz) divided by W, [15] D, [16] theta in degrees,
- *  [17] min(L^2 - tr C), [18] min leading minor of C, [19] max |u|, [20] flags.
+ *  [17] min(L^2 - tr C), [18] min leading minor of C, [19] max |u|, [20] flags,
+ *  [21] mean of tr C - 3 over the polymer phase weighted by the feedback modulation.
  * D = (a - b)/(a + b) and theta = angle of the major axis with x, from the x-y block
  * of the second-moment tensor (Sec. 4, deformation parameter and orientation). */
 void orc_diagnostics(orc_t *o, double *out) {
@@ -533,10 +534,10 @@ void orc_diagnostics(orc_t *o, double *out) {
     int saved = o->flags;
     derived_fields(o);
     o->flags = saved;
-    for (int k = 0; k < 21; k++) out[k] = 0.0;
+    for (int k = 0; k < 22; k++) out[k] = 0.0;
     double mass[2] = {0, 0}, mom[3] = {0, 0, 0};
     double Wt = 0, sx = 0, sy = 0, sz = 0;
-    double minL = INFINITY, minM = INFINITY, maxu = 0;
+    double minL = INFINITY, minM = INFINITY, maxu = 0, pex = 0, pw = 0;
     for (int z = 0; z < o->nz; z++)
         for (int y = 0; y < o->ny; y++)
             for (int x = 0; x < o->nx; x++) {
@@ -551,6 +552,9 @@ void orc_diagnostics(orc_t *o, double *out) {
                 Wt += w; sx += w * x; sy += w * y; sz += w * z;
                 double c[6];
                 for (int k = 0; k < 6; k++) c[k] = o->C[k * N + n];
+                double mp = modulation(o, o->phi[n]);
+                pex += mp * (c[0] + c[1] + c[2] - 3.0);
+                pw += mp;
                 double l = o->L2 - (c[0] + c[1] + c[2]);
                 if (l < minL) minL = l;
                 double m1 = c[0], m2 = c[0] * c[1] - c[3] * c[3];
@@ -586,6 +590,7 @@ void orc_diagnostics(orc_t *o, double *out) {
     for (int k = 0; k < 6; k++) out[9 + k] = M[k];
     out[15] = D; out[16] = theta; out[17] = minL; out[18] = minM; out[19] = maxu;
     out[20] = (double)o->flags;
+    out[21] = pw > 0 ? pex / pw : 0.0;
 }
 
 /* ---------------------------------------------------------- helpers for pins */

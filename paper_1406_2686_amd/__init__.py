@@ -54,7 +54,8 @@ class Diag(ctypes.Structure):
                 ("M", ctypes.c_double * 6), ("D", ctypes.c_double), ("theta_deg", ctypes.c_double),
                 ("min_L2_minus_trC", ctypes.c_double), ("min_minor", ctypes.c_double),
                 ("max_u", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("step", ctypes.c_int64)]
+                ("reserved", ctypes.c_uint32), ("step", ctypes.c_int64),
+                ("poly_trace_excess", ctypes.c_double)]
 
     def to_dict(self):
         return {"mass_A": self.mass[0], "mass_B": self.mass[1], "mom_x": self.momentum[0],
@@ -63,7 +64,8 @@ class Diag(ctypes.Structure):
                 "Mxx": self.M[0], "Myy": self.M[1], "Mzz": self.M[2], "Mxy": self.M[3],
                 "Mxz": self.M[4], "Myz": self.M[5], "D": self.D, "theta_deg": self.theta_deg,
                 "min_L2_minus_trC": self.min_L2_minus_trC, "min_minor": self.min_minor,
-                "max_u": self.max_u, "flags": int(self.flags), "step": int(self.step)}
+                "max_u": self.max_u, "flags": int(self.flags), "step": int(self.step),
+                "poly_trace_excess": self.poly_trace_excess}
 
 
 class Tuning(ctypes.Structure):

@@ -8,8 +8,9 @@
 // Record: [0] sum rho_A, [1] sum rho_B, [2..4] sum rho u, [5] W = sum w with
 // w = max(phi, 0), [6..8] sum w x, [9..14] raw second moments sum w x_i x_j
 // (xx, yy, zz, xy, xz, yz), [15] min(L^2 - tr C), [16] min leading minor of C,
-// [17] max |u|.  Sec. 4.1 defines D and theta from the droplet's axes; the host forms
-// them from the central moments.
+// [17] max |u|, [18] sum m (tr C - 3), [19] sum m with m the polymer-phase weight
+// (f+(phi), f-(phi), 1 or 0 as for the feedback).  Sec. 4.1 defines D and theta from the
+// droplet's axes; the host forms them from the central moments.
 #include <float.h>
 
 #include "d3q19.h"
@@ -110,6 +111,14 @@ __global__ __launch_bounds__(kDB) void k_diag_stage1(DevParams p, const float* _
                           c[4] * (c[3] * c[5] - c[1] * c[4]);
         acc[16] = fmin(acc[16], fmin(c[0], fmin(m2, m3)));
         acc[17] = fmax(acc[17], sqrt(ux * ux + uy * uy + uz * uz));
+        double mp = 0.0;
+        if (p.phase == 3) mp = 1.0;
+        else if (p.phase == 1 || p.phase == 2) {
+            const double t = tanh(phi * (double)p.inv_delta);
+            mp = p.phase == 1 ? 0.5 * (1.0 + t) : 0.5 * (1.0 - t);
+        }
+        acc[18] += mp * (c[0] + c[1] + c[2] - 3.0);
+        acc[19] += mp;
     }
     block_reduce_store(acc, part + (int64_t)blockIdx.x * kDiagVals);
 }

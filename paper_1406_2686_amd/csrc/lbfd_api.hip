@@ -461,6 +461,7 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
     out->max_u = r[17];
     out->flags = c->flags_seen;
     out->step = c->steps;
+    out->poly_trace_excess = r[19] > 0.0 ? r[18] / r[19] : 0.0;
     return LBFD_OK;
 }
 

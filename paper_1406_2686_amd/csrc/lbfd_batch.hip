@@ -326,10 +326,15 @@ lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit
         if (st != LBFD_OK) return st;
         const int64_t n = std::min<int64_t>(crit->every, max_steps - t);
         st = lbfd_batch_step(b, n);
-        if (st != LBFD_OK) return st;
+        if (st != LBFD_OK && st != LBFD_ENONFINITE && st != LBFD_EEXTENSIBILITY && st != LBFD_ENOTSPD) return st;
         t += n;
         for (int i = 0; i < b->n; ++i) {
             if (!act[i]) continue;
+            if (b->inst[i]->flags_seen) {  // a faulting instance is retired, not repaired
+                act[i] = 0;
+                steady_step[i] = -2;
+                continue;
+            }
             st = lbfd_diagnostics(b->inst[i], &out[i]);
             if (st != LBFD_OK) return bfail(b, st, lbfd_last_error(b->inst[i]));
             hist[i].push_back(out[i].D);

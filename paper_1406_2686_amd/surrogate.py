@@ -1,0 +1,178 @@
+"""Surrogate-accelerated droplet sweeps.
+
+A sweep solves many droplet-in-shear lattices (capillary number Ca, Deborah number De,
+viscosity ratio lambda, confinement 2R/H, extensibility L^2) to their steady shape.  The
+lattice solver is the reference; this module adds a learned shortcut:
+
+* ``solve``: run lattices to steady D with the batched solver (one launch per step over
+  all unfinished instances, steady ones retired) and collect D, theta and the polymer
+  stretch a = mean(tr C - 3) over the polymer phase;
+* ``Surrogate``: the 5-128-128-3 network (hand-written GPU kernels) trained on such solves,
+  mapping (Ca, De, lambda, 2R/H, log L^2) to (D, theta, a);
+* ``warm_fields``: initial fields for a solve started from a prediction -- an ellipsoidal
+  droplet with the predicted deformation and orientation (Sec. 4.1 definitions of D and
+  theta) and the predicted stretch in the polymer phase, shaped like the steady-shear
+  conformation of Sec. 3.1 (eqs. lindner, lindner2).
+
+The network never replaces the solver: every warm-started case is still solved to steady
+state, and the solver's D judges the prediction.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+FEATURES = ("Ca", "De", "lambda", "2R/H", "log L2")
+
+
+def features(cases) -> np.ndarray:
+    return np.array([[c["Ca"], c["De"], c["lam"], 2.0 * c["R"] / c["ny"], math.log(c["L2"])] for c in cases],
+                    dtype=np.float64)
+
+
+def lindner_deviation(Lam: float, L2: float) -> np.ndarray:
+    """Steady homogeneous shear conformation minus I, components (xx, yy, zz, xy, xz, yz):
+    sigma_P has xx = 1 + N, xy = S, yy = zz = 1 with S, N from the closed forms of Sec. 3.1,
+    and C = sigma_P / Z, Z = (L^2 + N)/L^2."""
+    a = L2 / 6.0
+    sh = math.sinh(math.asinh(Lam * L2 / 4.0 * a ** -1.5) / 3.0)
+    S = 2.0 * math.sqrt(a) * sh
+    N = 8.0 * a * sh * sh
+    Z = (L2 + N) / L2
+    return np.array([(1 + N) / Z - 1, 1 / Z - 1, 1 / Z - 1, S / Z, 0.0, 0.0])
+
+
+def shear_conformation_with_stretch(amp: float, L2: float) -> np.ndarray:
+    """Steady-shear conformation deviation whose trace excess tr C - 3 equals ``amp``: the
+    trace grows monotonically with Lambda, so Lambda is found by bisection.  Being a
+    steady-shear state, the result is positive definite with tr C < L^2."""
+    if not amp > 0:
+        return np.zeros(6)
+    hi = 1.0
+    while lindner_deviation(hi, L2)[:3].sum() < amp and hi < 1e8:
+        hi *= 2.0
+    lo = 0.0
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        if lindner_deviation(mid, L2)[:3].sum() < amp:
+            lo = mid
+        else:
+            hi = mid
+    return lindner_deviation(lo, L2)
+
+
+def warm_fields(wl: dict, D: float, theta_deg: float, amp: float):
+    """Initial (rho, u, C) of a droplet workload started from a predicted steady state:
+    ellipsoid with semi-axes R sqrt((1+D)/(1-D)), R sqrt((1-D)/(1+D)), R (volume kept),
+    major axis at theta from x in the x-y plane; in the polymer phase C is the steady-shear
+    conformation whose trace excess equals the predicted amp."""
+    g = wl["grid"]
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    meta = wl["meta"]
+    R = meta["R"]
+    D = float(np.clip(D, 0.0, 0.6))
+    a = R * math.sqrt((1 + D) / (1 - D))
+    b = R * math.sqrt((1 - D) / (1 + D))
+    t = math.radians(theta_deg)
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    dx, dy, dz = X.ravel() - (nx - 1) / 2, Y.ravel() - (ny - 1) / 2, Z.ravel() - (nz - 1) / 2
+    p = dx * math.cos(t) + dy * math.sin(t)
+    q = -dx * math.sin(t) + dy * math.cos(t)
+    inside = (p / a) ** 2 + (q / b) ** 2 + (dz / R) ** 2 < 1.0
+    rho_in, rho_out = wl["rho"].max(), wl["rho"].min()
+    rho = np.empty((2, X.size))
+    rho[0] = np.where(inside, rho_in, rho_out)
+    rho[1] = np.where(inside, rho_out, rho_in)
+    u = wl["u"].copy()
+    C = np.zeros((6, X.size))
+    C[:3] = 1.0
+    prm = wl["params"]
+    if prm["polymer_phase"] in ("A", "B") and amp > 0:
+        dev = shear_conformation_with_stretch(min(float(amp), 0.5 * (prm["L2"] - 3.0)), prm["L2"])
+        region = inside if prm["polymer_phase"] == "A" else ~inside
+        C += np.outer(dev, region.astype(np.float64))
+    return rho, u, C
+
+
+def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256, warm=None):
+    """Batched solves to steady D.  ``warm``: optional list of (D, theta, amp) predictions
+    (initial fields from warm_fields).  Returns per-case arrays and the wall time."""
+    import torch
+
+    n = len(wls)
+    out = {"D": np.zeros(n), "theta": np.zeros(n), "amp": np.zeros(n), "steady_step": np.zeros(n, dtype=np.int64),
+           "flags": np.zeros(n, dtype=np.int64)}
+    t0 = time.perf_counter()
+    for s0 in range(0, n, chunk):
+        part = wls[s0:s0 + chunk]
+        if warm is not None:
+            part = [dict(w, **dict(zip(("rho", "u", "C"), warm_fields(w, *warm[s0 + i]))))
+                    for i, w in enumerate(part)]
+        b = lb.Batch(part)
+        diags, ss = b.run_to_steady(every=every, window=window, tol=tol, max_steps=max_steps)
+        for i, (d, s) in enumerate(zip(diags, ss)):
+            k = s0 + i
+            out["D"][k] = d["D"]
+            out["theta"][k] = d["theta_deg"]
+            out["amp"][k] = d["poly_trace_excess"]
+            out["steady_step"][k] = s
+            out["flags"][k] = d["flags"]
+        b.close()
+        del b
+        torch.cuda.synchronize()
+    out["wall_s"] = time.perf_counter() - t0
+    return out
+
+
+def solve_plain(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000):
+    """Reference sweep: one lattice at a time, cold start, same steady test."""
+    import torch
+
+    n = len(wls)
+    D = np.zeros(n)
+    steps = np.zeros(n, dtype=np.int64)
+    lag = window // every
+    t0 = time.perf_counter()
+    for k, wl in enumerate(wls):
+        lat = lb.from_workload(wl)
+        hist = []
+        t = 0
+        steps[k] = -1
+        while t < max_steps:
+            st = lat.step_status(every)
+            t += every
+            d = lat.diagnostics()
+            if st != 0:
+                steps[k] = -2
+                break
+            hist.append(d["D"])
+            if len(hist) > lag and abs(hist[-1] - hist[-1 - lag]) < tol:
+                steps[k] = t
+                break
+        D[k] = d["D"]
+        lat.close()
+    torch.cuda.synchronize()
+    return {"D": D, "steady_step": steps, "wall_s": time.perf_counter() - t0}
+
+
+class Surrogate:
+    """Standardised inputs/outputs around the GPU network."""
+
+    def __init__(self, lb, seed=0, max_train=4096):
+        self.net = lb.MLP(max_batch=512, max_train=max_train, seed=seed)
+        self.xm = self.xs = self.ym = self.ys = None
+
+    def fit(self, X, Y, epochs=400, batch=128, lr=2e-3, seed=0):
+        X = np.asarray(X, np.float64)
+        Y = np.asarray(Y, np.float64)
+        self.xm, self.xs = X.mean(0), X.std(0) + 1e-12
+        self.ym, self.ys = Y.mean(0), Y.std(0) + 1e-12
+        return self.net.train((X - self.xm) / self.xs, (Y - self.ym) / self.ys, epochs=epochs, batch=batch,
+                              lr=lr, seed=seed)
+
+    def predict(self, X) -> np.ndarray:
+        """BF16 inference, outputs (D, theta_deg, amp)."""
+        Z = self.net.infer_bf16((np.asarray(X, np.float64) - self.xm) / self.xs)
+        return Z.astype(np.float64) * self.ys + self.ym

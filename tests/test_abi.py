@@ -52,4 +52,4 @@ def test_structs_match_header_layout():
 
     assert ctypes.sizeof(lb.Grid) == 16
     assert ctypes.sizeof(lb.Params) == 8 * 6 + 8 + 8 * 3
-    assert ctypes.sizeof(lb.Diag) == 8 * (2 + 3 + 1 + 3 + 6 + 5) + 8 + 8
+    assert ctypes.sizeof(lb.Diag) == 8 * (2 + 3 + 1 + 3 + 6 + 5) + 8 + 8 + 8

@@ -204,18 +204,19 @@ def random_state(nx, ny, nz, ncomp, seed, amp_rho=0.05, amp_u=0.02, amp_C=0.2):
     return rho, u, C
 
 
-def sweep_cases(n=64, seed=3, sigma=None, G=None):
+def sweep_cases(n=64, seed=3, scale=1.0):
     """Droplet-in-shear sweep instances drawn with numpy.random.default_rng(seed):
     N_x = N_z in {64, 128, 192}, N_y in {32, 48, 64}, R ~ U{8..24} subject to 2R/H <= 0.75
     and 4R <= N_x, Ca ~ U[0.05, 0.4], De ~ logU[0.1, 2], viscosity ratio lambda ~
     logU[0.5, 2] (tau_A = 1/2 + lambda (tau_B - 1/2), tau_B = 1), L^2 in {50, 100, 400}, and
-    the polymer in the droplet or the matrix by a coin flip."""
+    the polymer in the droplet or the matrix by a coin flip.  ``scale`` shrinks every length
+    (grid and radius) by the same factor."""
     rng = np.random.default_rng(seed)
     cases = []
     while len(cases) < n:
-        nxz = int(rng.choice([64, 128, 192]))
-        ny = int(rng.choice([32, 48, 64]))
-        R = int(rng.integers(8, 25))
+        nxz = int(round(int(rng.choice([64, 128, 192])) * scale))
+        ny = int(round(int(rng.choice([32, 48, 64])) * scale))
+        R = int(round(int(rng.integers(8, 25)) * scale))
         Ca = float(rng.uniform(0.05, 0.4))
         De = float(np.exp(rng.uniform(np.log(0.1), np.log(2.0))))
         lam = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
