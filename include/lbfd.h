@@ -56,7 +56,8 @@ typedef int32_t lbfd_status;
 typedef struct lbfd_ctx lbfd_ctx;
 
 typedef struct {
-    int32_t nx, ny, nz; /* lattice nodes; ny >= 3 (wall-normal), nx, nz >= 1          */
+    int32_t nx, ny, nz; /* lattice nodes; ny >= 3 (wall-normal), nx, nz >= 1, and      */
+                        /* nx*ny*nz < 2^30 (a field's byte offsets fit in 32 bits)     */
     int32_t ncomp;      /* 1 or 2 Shan-Chen components (A, B)                          */
 } lbfd_grid;
 
@@ -155,7 +156,7 @@ lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
 /* Launch shape of the step.  path: LBFD_PATH_FUSED (one pass over HBM per step, the
  * default) or LBFD_PATH_SPLIT (three passes: moments, forces, collide; same arithmetic,
  * kept as a cross-check).  tile: LBFD_TILE_32x8 / 32x16 / 16x16 (x by y nodes per
- * workgroup of the fused pass; with two components 32x16 runs as 32x8).  zchunk: planes per workgroup along z, 0 = automatic.
+ * workgroup of the fused pass; 32x16 runs as 32x8).  zchunk: planes per workgroup along z, 0 = automatic.
  * Results are identical for every tile and zchunk; only speed changes. */
 #define LBFD_PATH_FUSED 0
 #define LBFD_PATH_SPLIT 1

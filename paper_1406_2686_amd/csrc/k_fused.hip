@@ -16,8 +16,9 @@
 //      upwind advection, G^T C + C G with central G_ij = d_i u_j, Peterlin relaxation.
 // Every stage reads time level n only, so HBM sees each population and C component read
 // once and written once per step: 2 x ncomp x 19 x 4 + 2 x 6 x 4 bytes per node.  The halo
-// re-reads of neighbouring tiles hit L2: blocks are remapped so that each XCD owns a
-// contiguous range of tiles, x-tile fastest.
+// re-reads of neighbouring tiles are meant to hit a cache: blocks are mapped so that the
+// tiles running together on one XCD form a compact group and the groups running together
+// on the chip form a band (tile_of_block).
 //
 // Ghost rules at the y walls (same as the host-visible definition of the method):
 // densities copy the wall layer, C is extrapolated linearly, u is reflected through the
@@ -35,6 +36,36 @@ __device__ __forceinline__ int64_t xcd_remap_f(int64_t b, int64_t nb) {
     return (b & 7) * per + (b >> 3);
 }
 
+// Block -> (x tile, y tile, z chunk).  The hardware hands block b to XCD b % 8 and each
+// XCD starts its blocks in order, 32 at a time (one per CU at this kernel's occupancy).
+// Generation g of 256 blocks (32 per XCD) gets 256 consecutive logical indices, XCD k the
+// k-th run of 32; logical indices walk groups of gxw x gyh tiles (x fastest inside a
+// group, groups x-fastest, then group rows, then z chunks).  A tile's halo lines are then
+// the own lines of tiles that run at the same time on the same XCD (L2) or on a
+// neighbouring one (memory-side cache) instead of lines last touched a generation ago.
+// Blocks beyond the last whole generation keep their index.  The map is a bijection.
+__device__ __forceinline__ void tile_of_block(int64_t b, int64_t nb, int ntx, int nty, int gxw, int gyh, int& tx,
+                                              int& ty, int& zc) {
+    int64_t L = b;
+    const int64_t full = nb - nb % 256;
+    if (b < full) {
+        const int64_t slot = b >> 3;
+        L = (slot >> 5) * 256 + (b & 7) * 32 + (slot & 31);
+    }
+    const int64_t per = (int64_t)ntx * nty;
+    zc = (int)(L / per);
+    int64_t r = L - (int64_t)zc * per;
+    const int64_t rowsz = (int64_t)ntx * gyh;
+    const int gyi = (int)(r / rowsz);
+    r -= (int64_t)gyi * rowsz;
+    const int h = min(gyh, nty - gyi * gyh);
+    const int gxi = (int)(r / ((int64_t)gxw * h));
+    r -= (int64_t)gxi * gxw * h;
+    const int w = min(gxw, ntx - gxi * gxw);
+    tx = gxi * gxw + (int)(r % w);
+    ty = gyi * gyh + (int)(r / w);
+}
+
 __device__ __forceinline__ int wrapn(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
@@ -45,13 +76,6 @@ __device__ __forceinline__ int wrapn(int v, int n) {
 // never reads global data written by another thread of the same launch, so completing the
 // LDS operations (lgkmcnt(0)) before s_barrier is all the ordering it needs.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-__device__ __forceinline__ float modulation_f(int phase, float phi, float inv_delta) {
-    if (phase == 3) return 1.0f;
-    if (phase == 0) return 0.0f;
-    const float t = tanhf(phi * inv_delta);
-    return phase == 1 ? 0.5f * (1.0f + t) : 0.5f * (1.0f - t);
-}
 
 // R2 halo position k (0 <= k < 4*TX + 4*TY + 16) -> local (lx, ly) in [-2, TX+2) x [-2, TY+2)
 template <int TX, int TY>
@@ -99,11 +123,13 @@ struct FusedTile {
     static constexpr int W1 = TX + 2, H1 = TY + 2, A1 = W1 * H1;
     static constexpr int NH2 = A2 - NT;  // R2 halo nodes
     static constexpr int NH1 = A1 - NT;  // R1 halo nodes
-    float rho[3][NC][A2];  // delta rho per component (ring over planes)
-    float cs[3][8][A2];    // D = C - I (6), s, s1 (ring over planes)
-    float u[3][3][A1];     // total j (after A2), u (after B) (ring over planes)
-    float jc[NC][3][A1];   // momentum per component of the entering plane
-    float Fo[NC][3][NT];   // species forces of the tile nodes, phase B -> C
+    float rho[3][NC][A2];       // delta rho per component (ring over planes)
+    float cs[3][8][A2];         // D = C - I (6), s, s1 (ring over planes)
+    float u[3][3][A1];          // total j (after A2), u (after B) (ring over planes)
+    float jc[NC][3][A1];        // momentum per component of the entering plane
+    float Fo[NC][3][NT];        // species forces of the tile nodes, phase B -> C
+    float fpl[2][NT];           // f+(phi) of the tile nodes, planes q and q-1
+    float pop[2][NC][kQ][NT];   // own populations, planes q and q-1
 };
 
 // Populations of one component and (optionally) D of one node, as loaded.
@@ -112,22 +138,34 @@ struct NodeLoad {
     float d[6];
 };
 
-__device__ __forceinline__ void issue_load(const float* __restrict__ hs, const float* __restrict__ D, int64_t N,
-                                           int64_t n, bool with_d, NodeLoad& v) {
+// A field is addressed as a wave-uniform base plus a 32-bit byte offset (grids hold fewer
+// than 2^30 nodes), which keeps addresses out of 64-bit vector arithmetic.
+__device__ __forceinline__ float ld_off(const float* __restrict__ base, uint32_t boff) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
+}
+__device__ __forceinline__ void st_off(float* __restrict__ base, uint32_t boff, float v) {
+    // streaming store: the next step reads it, this launch does not
+    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff));
+}
+
+__device__ __forceinline__ void issue_load(const float* __restrict__ hs, const float* __restrict__ D, uint32_t N,
+                                           uint32_t n, bool with_d, NodeLoad& v) {
+    const uint32_t bo = n * 4u;
 #pragma unroll
-    for (int a = 0; a < kQ; ++a) v.f[a] = hs[a * N + n];
+    for (int a = 0; a < kQ; ++a) v.f[a] = ld_off(hs + (size_t)a * N, bo);
     if (with_d) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) v.d[k] = D[k * N + n];
+        for (int k = 0; k < 6; ++k) v.d[k] = ld_off(D + (size_t)k * N, bo);
     }
 }
 
 // Phase A1 for one (node, component) of plane q: delta rho and momentum of this component,
-// D when with_d.  Positions beyond a wall hold the wall layer's values (densities copy
-// the wall layer; C and the stress are replaced in phase A2).
-template <int NC, int TX, int TY>
-__device__ __forceinline__ void phase_a1(FusedTile<NC, TX, TY>& L, int sq, int c, int lx, int ly, bool with_d,
-                                         const NodeLoad& v) {
+// D when with_d, and for an own node the populations themselves (collided one plane
+// later).  Positions beyond a wall hold the wall layer's values (densities copy the wall
+// layer; C and the stress are replaced in phase A2).
+template <int NC, int TX, int TY, bool OWN>
+__device__ __forceinline__ void phase_a1(FusedTile<NC, TX, TY>& L, int sq, int s2, int c, int nid, int lx, int ly,
+                                         bool with_d, const NodeLoad& v) {
     using T = FusedTile<NC, TX, TY>;
     float sum = v.f[0];
 #pragma unroll
@@ -152,13 +190,18 @@ __device__ __forceinline__ void phase_a1(FusedTile<NC, TX, TY>& L, int sq, int c
         L.jc[c][1][i1] = jy;
         L.jc[c][2][i1] = jz;
     }
+    if (OWN) {
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) L.pop[s2][c][a][nid] = v.f[a];
+    }
 }
 
 // Phase A2 for one R2 position of plane q: wall ghosts of C (linear extrapolation from the
-// two wall-adjacent layers, Sec. 2 boundary condition of C), the stress coefficients
-// s = (eta_p/tau_p) m(phi) f(r), s1 = (eta_p/tau_p) m(phi) (f(r) - 1), and the total momentum.
+// two wall-adjacent layers, Sec. 2 boundary condition of C), f+(phi), the stress
+// coefficients s = (eta_p/tau_p) m(phi) f(r), s1 = (eta_p/tau_p) m(phi) (f(r) - 1), and the
+// total momentum.
 template <int NC, int TX, int TY>
-__device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, TY>& L, int sq, int y0, int k,
+__device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, TY>& L, int sq, int s2, int y0, int k,
                                          unsigned& bad) {
     using T = FusedTile<NC, TX, TY>;
     const int lx = k % T::W2 - 2, ly = k / T::W2 - 2;
@@ -181,11 +224,18 @@ __device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, T
         const float rb = p.rho0[1] + L.rho[sq][NC - 1][i2];
         phi = (ra - rb) / (ra + rb);
     }
+    // f+-(phi) = (1 +- tanh(phi/Delta))/2 (Sec. 2, smoothing of the viscosity and of the
+    // polymer feedback)
+    const float th = (NC == 2 || p.phase == 1 || p.phase == 2) ? tanhf(phi * p.inv_delta) : 0.0f;
+    float m = 0.0f;
+    if (p.phase == 3) m = 1.0f;
+    else if (p.phase == 1) m = 0.5f * (1.0f + th);
+    else if (p.phase == 2) m = 0.5f * (1.0f - th);
     const float trd = dv[0] + dv[1] + dv[2];
     const float den = p.L2m3 - trd;
     if (!(den > 0.0f) && gy >= -1 && gy <= p.ny) bad |= 2u;
     const float inv = 1.0f / den;
-    const float pm = p.pstress * modulation_f(p.phase, phi, p.inv_delta);
+    const float pm = p.pstress * m;
     // ghost rows are written only by this thread and read after the next barrier
     if (gy == -1 || gy == p.ny) {
 #pragma unroll
@@ -193,6 +243,7 @@ __device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, T
     }
     L.cs[sq][6][i2] = pm * p.L2m3 * inv;
     L.cs[sq][7][i2] = pm * trd * inv;
+    if (NC == 2 && lx >= 0 && lx < TX && ly >= 0 && ly < TY) L.fpl[s2][ly * TX + lx] = 0.5f * (1.0f + th);
     if (lx >= -1 && lx <= TX && ly >= -1 && ly <= TY) {
         const int i1 = (ly + 1) * T::W1 + lx + 1;
 #pragma unroll
@@ -277,13 +328,15 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     using T = FusedTile<NC, TX, TY>;
     static_assert(T::NH2 <= T::NT, "one R2 halo node per thread at most");
     static_assert(T::A1 <= 2 * T::NTH, "phase B covers the R1 region in two passes at most");
+    static_assert(T::NT % 64 == 0, "a wavefront never straddles two components");
 
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const int64_t N = p.N;
-    const int64_t plane = (int64_t)nx * ny;
+    const uint32_t N = (uint32_t)p.N;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
 
     const int tid = threadIdx.x;
-    const int comp = tid / T::NT;   // component this thread loads and collides
+    // component this thread loads and collides; uniform across the wavefront
+    const int comp = __builtin_amdgcn_readfirstlane(tid / T::NT);
     const int nid = tid % T::NT;    // tile node of this thread
     const int olx = nid % TX, oly = nid / TX;
     const int ogx = x0 + olx, ogy = y0 + oly;
@@ -291,8 +344,9 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     const int oi2 = (oly + 2) * T::W2 + olx + 2;
     const int oi1 = (oly + 1) * T::W1 + olx + 1;
     const int ogxw = wrapn(ogx, nx);
-    const int64_t own_xy = (int64_t)min(ogy, ny - 1) * nx + ogxw;
-    const float* hs = h + (int64_t)comp * kQ * N;
+    const uint32_t own_xy = (uint32_t)min(ogy, ny - 1) * (uint32_t)nx + (uint32_t)ogxw;
+    const float* hs = h + (size_t)comp * kQ * N;
+    float* hns = hn + (size_t)comp * kQ * N;
     const bool fene = comp == 0;            // FENE-P and own C handled by component-0 threads
     const bool halo_d = comp == NC - 1;      // halo C loaded by the last component's threads
 
@@ -301,50 +355,45 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     int hlx = 0, hly = 0;
     if (has_halo) halo2_pos<TX, TY>(nid, hlx, hly);
     const int hgy = y0 + hly;
-    const int64_t halo_xy = (int64_t)(hgy < 0 ? 0 : (hgy >= ny ? ny - 1 : hgy)) * nx + wrapn(x0 + hlx, nx);
+    const uint32_t halo_xy = (uint32_t)(hgy < 0 ? 0 : (hgy >= ny ? ny - 1 : hgy)) * (uint32_t)nx +
+                             (uint32_t)wrapn(x0 + hlx, nx);
+
+    // streaming targets of the own node that do not depend on the plane
+    const uint32_t xcol[3] = {(uint32_t)(ogxw == 0 ? nx - 1 : ogxw - 1), (uint32_t)ogxw,
+                              (uint32_t)(ogxw + 1 == nx ? 0 : ogxw + 1)};
+    const uint32_t yrow = (uint32_t)min(ogy, ny - 1) * (uint32_t)nx;
 
     // own-column values of plane q-3 (their LDS ring slots are reused by plane q)
     float c_old[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float u_old[3] = {0.f, 0.f, 0.f};
     unsigned bad = 0u;
 
+    // plane q+1 is loaded while plane q is processed; the loads land in the registers that
+    // phase A1 has just emptied, so no copy (and no early wait) sits on the loop edge
     NodeLoad pf_own, pf_halo;
-    float held[kQ];  // own populations of plane q-1 (collided in phase C)
-#pragma unroll
-    for (int a = 0; a < kQ; ++a) held[a] = 0.0f;
     {
-        const int64_t zoff = (int64_t)wrapn(z0 - 2, nz) * plane;
+        const uint32_t zoff = (uint32_t)wrapn(z0 - 2, nz) * plane;
         issue_load(hs, D, N, zoff + own_xy, fene, pf_own);
         if (has_halo) issue_load(hs, D, N, zoff + halo_xy, halo_d, pf_halo);
     }
 
     for (int q = z0 - 2; q <= z1 + 1; ++q) {
         const int sq = ((q % 3) + 3) % 3;
+        const int s2 = q & 1;
         const bool do_c = q >= z0 + 1 && q <= z1 && active;
 
-        // ---------------- A1: consume plane q (prefetched) ----------------
-        phase_a1<NC, TX, TY>(L, sq, comp, olx, oly, fene, pf_own);
-        if (has_halo) phase_a1<NC, TX, TY>(L, sq, comp, hlx, hly, halo_d, pf_halo);
-        // own populations: plane q-1 (held since the previous plane) is collided in phase C,
-        // plane q is kept for the next one; each population is read from HBM once per step
-        float hv[kQ], cur[kQ];
-#pragma unroll
-        for (int a = 0; a < kQ; ++a) {
-            hv[a] = held[a];
-            cur[a] = pf_own.f[a];
-        }
-        const int r = wrapn(q - 1, nz);
-        const int64_t nself = (int64_t)r * plane + own_xy;
-        // prefetch plane q+1
+        // ---------------- A1: consume plane q, then request plane q+1 ----------------
+        phase_a1<NC, TX, TY, true>(L, sq, s2, comp, nid, olx, oly, fene, pf_own);
+        if (has_halo) phase_a1<NC, TX, TY, false>(L, sq, s2, comp, nid, hlx, hly, halo_d, pf_halo);
         if (q + 1 <= z1 + 1) {
-            const int64_t zoff = (int64_t)wrapn(q + 1, nz) * plane;
+            const uint32_t zoff = (uint32_t)wrapn(q + 1, nz) * plane;
             issue_load(hs, D, N, zoff + own_xy, fene, pf_own);
             if (has_halo) issue_load(hs, D, N, zoff + halo_xy, halo_d, pf_halo);
         }
         lds_barrier();
 
-        // ---------------- A2: ghosts, stress coefficients, total momentum ----------------
-        for (int k = tid; k < T::A2; k += T::NTH) phase_a2<NC, TX, TY>(p, L, sq, y0, k, bad);
+        // ---------------- A2: ghosts, f+, stress coefficients, total momentum ----------------
+        for (int k = tid; k < T::A2; k += T::NTH) phase_a2<NC, TX, TY>(p, L, sq, s2, y0, k, bad);
         lds_barrier();
 
         // ---------------- B: forces and velocity on plane q-1 (tile + 1 halo) -------------
@@ -374,60 +423,70 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
         lds_barrier();
 
         // ---------------- C: collide + stream plane q-1 (own node, own component) ----------
+        // BGK with the forcing source (eq. LB, Lambda = I/tau(phi)).  For an opposite pair
+        // (a, a+1) the equilibrium and the source split into parts even and odd in c, formed
+        // once per pair; each population is then relaxed as h - (h - h_eq)/tau + (1 -
+        // 1/(2 tau)) S, the form whose rounding keeps the species mass drift smallest.
         if (do_c) {
             const int sr = ((q - 1) % 3 + 3) % 3;
+            const int p2 = s2 ^ 1;
+            const int r = wrapn(q - 1, nz);
             float u[3], F[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 u[d] = L.u[sr][d][oi1];
                 F[d] = L.Fo[comp][d][nid];
             }
-            const float drA = L.rho[sr][0][oi2];
-            const float drB = NC == 2 ? L.rho[sr][NC - 1][oi2] : 0.0f;
-            const float drs = comp == 0 ? drA : drB;
-            const float rA = p.rho0[0] + drA;
-            const float rB = NC == 2 ? p.rho0[1] + drB : 0.0f;
-            const float rs = comp == 0 ? rA : rB;
+            const float drs = L.rho[sr][comp][oi2];
+            const float rs = (comp == 0 ? p.rho0[0] : p.rho0[1]) + drs;
             const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-            float tau = p.tauA;
-            if (NC == 2) {
-                const float phi = (rA - rB) / (rA + rB);
-                tau = p.tauB + (p.tauA - p.tauB) * 0.5f * (1.0f + tanhf(phi * p.inv_delta));
-            }
+            const float tau = NC == 2 ? p.tauB + (p.tauA - p.tauB) * L.fpl[p2][nid] : p.tauA;
             const float om = 1.0f / tau;
             const float cfac = 1.0f - 0.5f * om;
-            const int xp = ogxw + 1 == nx ? 0 : ogxw + 1;
-            const int xm = ogxw == 0 ? nx - 1 : ogxw - 1;
-            const int zp = r + 1 == nz ? 0 : r + 1;
-            const int zm = r == 0 ? nz - 1 : r - 1;
             const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-            float* hns = hn + (int64_t)comp * kQ * N;
-            float check = 0.0f;
+            const float b = -1.5f * uu;
+            const uint32_t zrow[3] = {(uint32_t)(r == 0 ? nz - 1 : r - 1) * plane, (uint32_t)r * plane,
+                                      (uint32_t)(r + 1 == nz ? 0 : r + 1) * plane};
+            const uint32_t bself = (zrow[1] + yrow + xcol[1]) * 4u;
+            float check;
+            {
+                const float w = wgt(0);
+                const float ha = L.pop[p2][comp][0][nid];
+                const float post = ha - om * (ha - w * (drs + rs * b)) + cfac * (w * (-3.0f * uF));
+                st_off(hns, bself, post);
+                check = post;
+            }
 #pragma unroll
-            for (int a = 0; a < kQ; ++a) {
-                const float ha = hv[a];
+            for (int a = 1; a < kQ; a += 2) {
+                const float w = wgt(a);
                 const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
                 const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
-                const float heq = wgt(a) * (drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
-                const float src = wgt(a) * (3.0f * (cF - uF) + 9.0f * cu * cF);
-                const float post = ha - om * (ha - heq) + cfac * src;
-                check += post;
-                const int yd = ogy + cy(a);
-                if (yd >= 0 && yd < ny) {
-                    const int xd = cx(a) == 0 ? ogxw : (cx(a) > 0 ? xp : xm);
-                    const int zd = cz(a) == 0 ? r : (cz(a) > 0 ? zp : zm);
-                    // streaming stores: the next step reads them, this launch does not
-                    __builtin_nontemporal_store(post, &hns[a * N + (int64_t)zd * plane + (int64_t)yd * nx + xd]);
-                } else {
-                    const float* uw = yd < 0 ? p.ub : p.ut;
-                    const float cuw = cx(a) * uw[0] + cz(a) * uw[2];
-                    __builtin_nontemporal_store(post - 6.0f * wgt(a) * rs * cuw, &hns[opp(a) * N + nself]);
+                const float ee = w * (drs + rs * (4.5f * cu * cu + b));  // equilibrium, even part
+                const float eo = (3.0f * w) * rs * cu;                   // equilibrium, odd part
+                const float se = w * (9.0f * cu * cF - 3.0f * uF);       // source, even part
+                const float so = (3.0f * w) * cF;                        // source, odd part
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int bq = a + e;
+                    const float ha = L.pop[p2][comp][bq][nid];
+                    const float heq = e == 0 ? ee + eo : ee - eo;
+                    const float src = e == 0 ? se + so : se - so;
+                    const float post = ha - om * (ha - heq) + cfac * src;
+                    check += post;
+                    const int yd = ogy + cy(bq);
+                    if (yd >= 0 && yd < ny) {
+                        const uint32_t dst = zrow[cz(bq) + 1] + yrow + (uint32_t)(cy(bq) * nx) + xcol[cx(bq) + 1];
+                        st_off(hns + (size_t)bq * N, dst * 4u, post);
+                    } else {
+                        // moving-wall bounce-back (Sec. 3.1 walls): the link returns as opp(bq)
+                        const float* uw = yd < 0 ? p.ub : p.ut;
+                        const float cuw = cx(bq) * uw[0] + cz(bq) * uw[2];
+                        st_off(hns + (size_t)opp(bq) * N, bself, post - 6.0f * wgt(bq) * rs * cuw);
+                    }
                 }
             }
             if (!isfinite(check)) bad |= 1u;
         }
-#pragma unroll
-        for (int a = 0; a < kQ; ++a) held[a] = cur[a];
 
         // ---------------- D: FENE-P on plane q-2 (own node, component-0 threads) ----------
         if (fene && q >= z0 + 2 && active) {
@@ -497,11 +556,11 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                     dnew[kk] = d0[kk] + (-adv[kk] + stv - relax);
                 }
             }
-            const int64_t nt = (int64_t)t * plane + own_xy;
+            const uint32_t bt = ((uint32_t)t * plane + own_xy) * 4u;
             float check = 0.0f;
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
-                __builtin_nontemporal_store(dnew[k], &Dn[k * N + nt]);
+                st_off(Dn + (size_t)k * N, bt, dnew[k]);
                 check += dnew[k];
             }
             if (!isfinite(check)) bad |= 1u;
@@ -528,16 +587,16 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
 }
 
 template <int NC, int TX, int TY>
-__global__ __launch_bounds__(NC* TX* TY, (NC == 1 ? 2 : 1)) void k_fused(
+__global__ __launch_bounds__(NC* TX* TY, 1) void k_fused(
     DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
     float* __restrict__ Dn, unsigned* __restrict__ flags, int zchunk) {
     __shared__ FusedTile<NC, TX, TY> L;
     const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
-    const int64_t bid = xcd_remap_f(blockIdx.x, gridDim.x);
-    const int tx_i = (int)(bid % ntx);
-    const int64_t rem = bid / ntx;
-    const int ty_i = (int)(rem % nty);
-    const int zc_i = (int)(rem / nty);
+    // groups of about 256 x 32 nodes
+    const int gxw = min(ntx, 256 / TX);
+    const int gyh = min(nty, max(1, 32 / gxw));
+    int tx_i, ty_i, zc_i;
+    tile_of_block(blockIdx.x, gridDim.x, ntx, nty, gxw, gyh, tx_i, ty_i, zc_i);
     const int z0 = zc_i * zchunk;
     fused_tile<NC, TX, TY>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0, min(z0 + zchunk, p.nz));
 }
@@ -547,7 +606,7 @@ __global__ __launch_bounds__(NC* TX* TY, (NC == 1 ? 2 : 1)) void k_fused(
 // buffer holding time level n is cur ^ parity, so a two-launch graph (parity 0, 1)
 // replays any even number of steps.
 template <int NC, int TX, int TY>
-__global__ __launch_bounds__(NC* TX* TY, (NC == 1 ? 2 : 1)) void k_fused_batch(
+__global__ __launch_bounds__(NC* TX* TY, 1) void k_fused_batch(
     const BatchInstance* __restrict__ inst, const WorkItem* __restrict__ work, int parity) {
     __shared__ FusedTile<NC, TX, TY> L;
     const int64_t bid = xcd_remap_f(blockIdx.x, gridDim.x);
@@ -578,9 +637,7 @@ hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, i
         else
             hipLaunchKernelGGL((k_fused_batch<2, 32, 8>), grid, dim3(512), 0, s, inst, work, parity);
     } else {
-        if (tile == 1)
-            hipLaunchKernelGGL((k_fused_batch<1, 32, 16>), grid, dim3(512), 0, s, inst, work, parity);
-        else if (tile == 2)
+        if (tile == 2)
             hipLaunchKernelGGL((k_fused_batch<1, 16, 16>), grid, dim3(256), 0, s, inst, work, parity);
         else
             hipLaunchKernelGGL((k_fused_batch<1, 32, 8>), grid, dim3(256), 0, s, inst, work, parity);
@@ -588,21 +645,20 @@ hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, i
     return hipGetLastError();
 }
 
-// tile extent of a tuning choice (two components run the 32x16 choice as 32x8)
+// tile extent of a tuning choice (the 32x16 choice runs as 32x8: a 32x16 tile with its
+// two planes of own populations would not fit in LDS)
 void fused_tile_shape(int ncomp, int tile, int* tx, int* ty) {
+    (void)ncomp;
     *tx = tile == 2 ? 16 : 32;
-    *ty = tile == 2 ? 16 : ((tile == 1 && ncomp == 1) ? 16 : 8);
+    *ty = tile == 2 ? 16 : 8;
 }
 
 hipError_t launch_fused(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s) {
     const int zc = t.zchunk > 0 ? t.zchunk : p.nz;
     if (p.nc == 2) {
-        // two components run one thread per (node, component): the 32x16 tile would need
-        // 1024 threads at half the registers, so it maps to 32x8
         if (t.tile == 2) return launch_fused_t<2, 16, 16>(p, b, zc, s);
         return launch_fused_t<2, 32, 8>(p, b, zc, s);
     }
-    if (t.tile == 1) return launch_fused_t<1, 32, 16>(p, b, zc, s);
     if (t.tile == 2) return launch_fused_t<1, 16, 16>(p, b, zc, s);
     return launch_fused_t<1, 32, 8>(p, b, zc, s);
 }

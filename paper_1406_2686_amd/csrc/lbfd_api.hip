@@ -31,7 +31,8 @@ bool grid_ok(const lbfd_grid* g) {
     if (g->nx < 1 || g->ny < 3 || g->nz < 1) return false;
     if (g->ncomp != 1 && g->ncomp != 2) return false;
     const int64_t N = (int64_t)g->nx * g->ny * g->nz;
-    return N / 256 < (int64_t)0x7fffffff;
+    // kernels address one field with 32-bit byte offsets
+    return N < ((int64_t)1 << 30);
 }
 
 Layout layout(const lbfd_grid* g) {
@@ -154,7 +155,7 @@ hipError_t compute_side_fields(lbfd_ctx* c) {
 // 53.5 at 16 planes per workgroup)
 int auto_zchunk(const lbfd_grid& g, int tile) {
     const int tx = tile == 2 ? 16 : 32;
-    const int ty = (tile == 1 && g.ncomp == 1) ? 16 : (tile == 2 ? 16 : 8);
+    const int ty = tile == 2 ? 16 : 8;
     const int64_t tiles = (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
     int64_t zc = ((int64_t)g.nz * tiles + 2047) / 2048;
     zc = std::min<int64_t>(std::max<int64_t>(zc, 8), 64);

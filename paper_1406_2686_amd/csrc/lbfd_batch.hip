@@ -423,8 +423,7 @@ lbfd_status lbfd_autotune(lbfd_ctx* c, int32_t reps, lbfd_tuning* best, double* 
     c->flags_seen |= saved;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBFD_EDEVICE;
-    std::vector<int> tiles = {LBFD_TILE_32x8, LBFD_TILE_16x16};
-    if (c->grid.ncomp == 1) tiles.push_back(LBFD_TILE_32x16);
+    const std::vector<int> tiles = {LBFD_TILE_32x8, LBFD_TILE_16x16};
     const int zcs[6] = {8, 16, 32, 64, 128, 256};
     Tuning win = c->tune;
     float best_ms = 1e30f;

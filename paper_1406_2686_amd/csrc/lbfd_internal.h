@@ -43,8 +43,8 @@ struct Box {
     int x0, y0, z0, bx, by, bz;
 };
 
-// Launch shape of the fused step: tile 0 = 32x8, 1 = 32x16, 2 = 16x16 (x by y nodes per
-// workgroup); zchunk = planes per workgroup along z (0 = all).  path 0 = fused single
+// Launch shape of the fused step: tile 0 = 32x8, 1 = 32x16 (runs as 32x8), 2 = 16x16 (x by y
+// nodes per workgroup); zchunk = planes per workgroup along z (0 = all).  path 0 = fused single
 // pass, 1 = three-pass split (moments, forces, collide).
 struct Tuning {
     int path;

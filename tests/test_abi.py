@@ -42,7 +42,8 @@ def test_state_bytes_validates_grid():
     b1 = lb.state_bytes(128, 64, 128, 2)
     # two population copies (2 x 19 FP32) and two C copies (6 FP32) at least
     assert b1 >= 128 * 64 * 128 * (2 * 2 * 19 + 2 * 6) * 4
-    for bad in [(16, 2, 16, 1), (0, 8, 8, 1), (8, 8, 8, 3), (8, 8, -1, 2)]:
+    # ny >= 3, ncomp in {1, 2}, positive extents, fewer than 2^30 nodes
+    for bad in [(16, 2, 16, 1), (0, 8, 8, 1), (8, 8, 8, 3), (8, 8, -1, 2), (1024, 1024, 1024, 1)]:
         with pytest.raises(lb.LbfdError):
             lb.state_bytes(*bad)
 
