@@ -30,6 +30,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def recorded_traffic(workload):
+    """HBM bytes per launch of the fused kernel on `workload`, from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    copy of known size).  Returned only while the kernel sources hash to the profiled ones;
+    a changed kernel gives None until it is profiled again."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_fused_{workload.replace('droplet_shear_', 'droplet_')}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic-record "):
+            rec = json.loads(line[len("traffic-record "):])
+    if not rec or rec.get("workload") != workload:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["sha256"]:
+        return None
+    rec["path"] = os.path.relpath(path, ROOT)
+    return rec
+
+
 def build_lattice(lb, workloads, nx, ny, nz, zchunk=16):
     """Create the droplet lattice and upload its fields slab by slab (host memory stays
     bounded for the 268M-node grid)."""
@@ -225,6 +250,8 @@ def main():
     mlups = N * K / wall / 1e6
     alg = ALG_BYTES[2] * N
     achieved = alg / (step_ms * 1e-3) / 1e9
+    rec = recorded_traffic(f"droplet_shear_{nx}x{ny}x{nz}")
+    traffic = None if rec is None else round(rec["bytes_per_launch"] / (step_ms * 1e-3) / 1e9, 1)
     mass_drift = max(abs(d1["mass_A"] - d0["mass_A"]) / d0["mass_A"],
                      abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"])
     out = {
@@ -236,9 +263,11 @@ def main():
                    "droplet_R": wl0["meta"]["R"], "polymer": "matrix (L2=400, De=1)",
                    "diag_every": args.diag_every, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_fused (the whole step, one launch per step)",
-                     "alg_bytes_per_node": ALG_BYTES[2], "event_ms_per_step": round(step_ms, 4)},
+                     "alg_bytes_per_node": ALG_BYTES[2], "event_ms_per_step": round(step_ms, 4),
+                     "traffic_bytes_per_launch": None if rec is None else rec["bytes_per_launch"],
+                     "traffic_source": None if rec is None else rec["path"]},
         "checks": {"fault_flags": flags, "mass_drift_rel": mass_drift, "D_final": d1["D"]},
     }
     lat.close()
