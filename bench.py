@@ -119,9 +119,12 @@ def copy_probe(torch, gib, reps=20):
 
 
 def sweep(lb, workloads, args):
-    """Time to steady D for a held-out set of droplet-in-shear cases: plain per-case solves
-    (cold start, one lattice at a time) vs one batched solve (cold) vs one batched solve
-    warm-started from the surrogate trained on batched solves of the training cases."""
+    """Time to an answer within |dD| <= 0.01 of the plain steady D for a held-out set of
+    droplet-in-shear cases.  Without the network: plain per-case solves (cold start, one
+    lattice at a time) and one batched cold solve.  With it: two networks (different seeds)
+    trained on batched solves of the training cases answer every held-out case; where they
+    disagree by more than 0.005 in D the case falls back to a batched solve started from
+    their mean prediction.  The plain solves judge every answer."""
     import numpy as np
 
     from paper_1406_2686_amd import surrogate as sg
@@ -132,44 +135,52 @@ def sweep(lb, workloads, args):
     wtrain = [workloads.sweep_workload(c) for c in train]
     wtest = [workloads.sweep_workload(c) for c in test]
     log(f"sweep: {len(train)} training / {len(test)} held-out cases, scale {args.scale}")
-    gen = sg.solve(lb, wtrain, **crit)
+    gen = sg.solve(lb, wtrain, progress=log, **crit)
     ok = gen["steady_step"] > 0
     log(f"training data: {ok.sum()} steady of {len(train)} in {gen['wall_s']:.1f} s")
     X = sg.features(train)[ok]
     Y = np.stack([gen["D"], gen["theta"], gen["amp"]], 1)[ok]
-    model = sg.Surrogate(lb, seed=1, max_train=max(4096, len(train)))
+    models = [sg.Surrogate(lb, seed=s, max_train=max(4096, len(train))) for s in (1, 2)]
     t0 = time.perf_counter()
-    loss = model.fit(X, Y, epochs=400, batch=128, lr=2e-3, seed=2)
+    losses = [m.fit(X, Y, epochs=400, batch=128, lr=2e-3, seed=s + 10) for s, m in enumerate(models)]
     t_train = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    pred = model.predict(sg.features(test))
-    t_pred = time.perf_counter() - t0
-    plain = sg.solve_plain(lb, wtest, **crit)
+    plain = sg.solve_plain(lb, wtest, progress=log, **crit)
     log(f"plain sweep: {plain['wall_s']:.1f} s")
-    cold = sg.solve(lb, wtest, **crit)
+    cold = sg.solve(lb, wtest, progress=log, **crit)
     log(f"batched cold sweep: {cold['wall_s']:.1f} s")
-    warm = sg.solve(lb, wtest, warm=[tuple(r) for r in pred], **crit)
-    log(f"batched warm sweep: {warm['wall_s']:.1f} s")
-    judge = plain["D"]
+    t0 = time.perf_counter()
+    Xt = sg.features(test)
+    p1, p2 = (m.predict(Xt) for m in models)
+    pred = 0.5 * (p1 + p2)
+    flag = np.abs(p1[:, 0] - p2[:, 0]) > 0.005
+    t_pred = time.perf_counter() - t0
+    answer = pred[:, 0].copy()
+    t_fb = 0.0
+    if flag.any():
+        idx = np.nonzero(flag)[0]
+        fb = sg.solve(lb, [wtest[i] for i in idx], warm=[tuple(pred[i]) for i in idx], progress=log, **crit)
+        answer[idx] = fb["D"]
+        t_fb = fb["wall_s"]
+    log(f"surrogate + fallback: {flag.sum()} of {len(test)} solved, {t_pred + t_fb:.2f} s")
     valid = plain["steady_step"] > 0
-    err_pred = np.abs(pred[:, 0] - judge)[valid]
-    err_warm = np.abs(warm["D"] - judge)[valid]
+    judge = plain["D"]
+    within = lambda d: float(np.mean(np.abs(d - judge)[valid] <= 0.01))
     out = {"metric": "sweep time-to-steady-D (|dD| <= 0.01 against plain solves)", "unit": "s",
-           "value": round(warm["wall_s"] + t_pred, 2), "higher_is_better": False, "n_gpus": 1,
+           "value": round(t_pred + t_fb, 3), "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic", "dtype": "f32 solver, bf16 surrogate inference",
            "config": {"workload": f"droplet sweep, grids x{args.scale} of 64-192 x 32-64",
                       "n_train": len(train), "n_test": len(test), **crit},
            "plain_per_case_s": round(plain["wall_s"], 2), "batched_cold_s": round(cold["wall_s"], 2),
-           "batched_warm_s": round(warm["wall_s"], 2), "surrogate_infer_s": round(t_pred, 4),
-           "training_data_s": round(gen["wall_s"], 2), "train_s": round(t_train, 2), "final_loss": loss,
-           "surrogate_within_0.01": float(np.mean(err_pred <= 0.01)),
-           "surrogate_mean_abs_dD": float(err_pred.mean()),
-           "warm_within_0.01": float(np.mean(err_warm <= 0.01)),
-           "steps_cold_mean": float(cold["steady_step"][cold["steady_step"] > 0].mean()),
-           "steps_warm_mean": float(warm["steady_step"][warm["steady_step"] > 0].mean()),
+           "surrogate_infer_s": round(t_pred, 4), "fallback_solve_s": round(t_fb, 2),
+           "fallback_cases": int(flag.sum()), "training_data_s": round(gen["wall_s"], 2),
+           "train_s": round(t_train, 2), "final_loss": losses,
+           "judged_cases": int(valid.sum()),
+           "within_0.01": {"surrogate_with_fallback": within(answer), "surrogate_alone": within(pred[:, 0]),
+                           "batched_cold": within(cold["D"])},
+           "surrogate_mean_abs_dD": float(np.abs(pred[:, 0] - judge)[valid].mean()),
            "unsteady_or_fault": {"plain": int((plain["steady_step"] <= 0).sum()),
                                  "cold": int((cold["steady_step"] <= 0).sum()),
-                                 "warm": int((warm["steady_step"] <= 0).sum())}}
+                                 "training": int((~ok).sum())}}
     print(json.dumps(out), flush=True)
 
 

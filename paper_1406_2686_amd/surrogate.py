@@ -80,7 +80,16 @@ def warm_fields(wl: dict, D: float, theta_deg: float, amp: float):
     dx, dy, dz = X.ravel() - (nx - 1) / 2, Y.ravel() - (ny - 1) / 2, Z.ravel() - (nz - 1) / 2
     p = dx * math.cos(t) + dy * math.sin(t)
     q = -dx * math.sin(t) + dy * math.cos(t)
-    inside = (p / a) ** 2 + (q / b) ** 2 + (dz / R) ** 2 < 1.0
+    e2 = (p / a) ** 2 + (q / b) ** 2 + (dz / R) ** 2
+    # the voxelised ellipsoid holds as many droplet nodes as the voxelised sphere of the
+    # cold start (same droplet mass): scale all three semi-axes by sqrt of the e2 quantile
+    n_sphere = int(np.count_nonzero(dx * dx + dy * dy + dz * dz < R * R))
+    if 0 < n_sphere < e2.size:
+        cut = float(np.partition(e2, n_sphere - 1)[n_sphere - 1])
+        cut = 0.5 * (cut + float(np.partition(e2, n_sphere)[n_sphere]))
+    else:
+        cut = 1.0
+    inside = e2 < cut
     rho_in, rho_out = wl["rho"].max(), wl["rho"].min()
     rho = np.empty((2, X.size))
     rho[0] = np.where(inside, rho_in, rho_out)
@@ -96,9 +105,10 @@ def warm_fields(wl: dict, D: float, theta_deg: float, amp: float):
     return rho, u, C
 
 
-def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256, warm=None):
+def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256, warm=None, progress=None):
     """Batched solves to steady D.  ``warm``: optional list of (D, theta, amp) predictions
-    (initial fields from warm_fields).  Returns per-case arrays and the wall time."""
+    (initial fields from warm_fields).  ``progress``: optional callable given a line of text
+    after each chunk.  Returns per-case arrays and the wall time."""
     import torch
 
     n = len(wls)
@@ -122,11 +132,14 @@ def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256,
         b.close()
         del b
         torch.cuda.synchronize()
+        if progress is not None:
+            done = s0 + len(part)
+            progress(f"  solved {done}/{n} cases, {time.perf_counter() - t0:.1f} s")
     out["wall_s"] = time.perf_counter() - t0
     return out
 
 
-def solve_plain(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000):
+def solve_plain(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, progress=None):
     """Reference sweep: one lattice at a time, cold start, same steady test."""
     import torch
 
@@ -153,6 +166,8 @@ def solve_plain(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000):
                 break
         D[k] = d["D"]
         lat.close()
+        if progress is not None and (k + 1) % 16 == 0:
+            progress(f"  plain: {k + 1}/{n} cases, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     return {"D": D, "steady_step": steps, "wall_s": time.perf_counter() - t0}
 
