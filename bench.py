@@ -123,8 +123,9 @@ def sweep(lb, workloads, args):
     droplet-in-shear cases.  Without the network: plain per-case solves (cold start, one
     lattice at a time) and one batched cold solve.  With it: two networks (different seeds)
     trained on batched solves of the training cases answer every held-out case; where they
-    disagree by more than 0.005 in D the case falls back to a batched solve started from
-    their mean prediction.  The plain solves judge every answer."""
+    disagree by more than 0.005 in D the case falls back to a batched cold solve.  The plain
+    solves judge every answer; `value` is the time of the fastest path whose answers are
+    all within the tolerance."""
     import numpy as np
 
     from paper_1406_2686_amd import surrogate as sg
@@ -158,15 +159,19 @@ def sweep(lb, workloads, args):
     t_fb = 0.0
     if flag.any():
         idx = np.nonzero(flag)[0]
-        fb = sg.solve(lb, [wtest[i] for i in idx], warm=[tuple(pred[i]) for i in idx], progress=log, **crit)
+        fb = sg.solve(lb, [wtest[i] for i in idx], progress=log, **crit)
         answer[idx] = fb["D"]
         t_fb = fb["wall_s"]
     log(f"surrogate + fallback: {flag.sum()} of {len(test)} solved, {t_pred + t_fb:.2f} s")
     valid = plain["steady_step"] > 0
     judge = plain["D"]
     within = lambda d: float(np.mean(np.abs(d - judge)[valid] <= 0.01))
+    paths = {"surrogate_with_fallback": (t_pred + t_fb, within(answer)),
+             "batched_cold": (cold["wall_s"], within(cold["D"])),
+             "plain": (plain["wall_s"], 1.0)}
+    best = min((t, k) for k, (t, w) in paths.items() if w >= 1.0)
     out = {"metric": "sweep time-to-steady-D (|dD| <= 0.01 against plain solves)", "unit": "s",
-           "value": round(t_pred + t_fb, 3), "higher_is_better": False, "n_gpus": 1,
+           "value": round(best[0], 3), "path": best[1], "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic", "dtype": "f32 solver, bf16 surrogate inference",
            "config": {"workload": f"droplet sweep, grids x{args.scale} of 64-192 x 32-64",
                       "n_train": len(train), "n_test": len(test), **crit},
