@@ -53,6 +53,13 @@ typedef int32_t lbfd_status;
 #define LBFD_POLYMER_B 2    /* m = f-(phi) = (1 - tanh(phi/Delta))/2   */
 #define LBFD_POLYMER_ALL 3  /* m = 1                                    */
 
+/* how the polymer stress T = (eta_p/tau_p) m(phi) (f(r) C - I) acts on the fluid */
+#define LBFD_COUPLING_FORCE 0  /* body force div T (central differences), split between the
+                                  species by rho_s/rho (Sec. 2, eq. NS); the default        */
+#define LBFD_COUPLING_STRESS 1 /* T_s = (rho_s/rho) T lowers the second moment of each
+                                  species' equilibrium (Sec. 2, eq. MODEtransformation):
+                                  E_a -= 4.5 w_a (c_a.T_s.c_a - tr T_s / 3); no body force  */
+
 typedef struct lbfd_ctx lbfd_ctx;
 
 typedef struct {
@@ -68,7 +75,7 @@ typedef struct {
     double delta;          /* smoothing width of f+-(phi) (Sec. 2, eq. smoothingvisco)  */
     double rho0[2];        /* storage shift per component (populations kept as f - w rho0) */
     int32_t polymer_phase; /* LBFD_POLYMER_*                                           */
-    int32_t reserved;
+    int32_t coupling;      /* LBFD_COUPLING_*; any other value is EINVAL               */
     double eta_p;          /* polymer viscosity (Sec. 2, eq. NS)                        */
     double tau_p;          /* polymer relaxation time in lattice steps (> 0)            */
     double L2;             /* FENE-P maximum extension squared (> 3)                    */

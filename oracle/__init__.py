@@ -21,6 +21,7 @@ _SRC = os.path.join(_HERE, "lbfd_oracle.c")
 _LIB = os.path.join(_HERE, "liblbfd_oracle.so")
 
 PHASE = {"none": 0, "A": 1, "B": 2, "all": 3}
+COUPLING = {"force": 0, "stress": 1}
 FLAG_NONFINITE, FLAG_EXTENSIBILITY, FLAG_NOT_SPD = 1, 2, 4
 
 DIAG_FIELDS = (
@@ -57,7 +58,7 @@ def lib():
         L.orc_destroy.argtypes = [P]
         L.orc_set_params.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_double]
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.orc_set_walls.argtypes = [P, D, D]
         L.orc_set_fields.argtypes = [P, D, D, D]
         L.orc_set_fields.restype = ctypes.c_int
@@ -71,6 +72,7 @@ def lib():
         L.orc_diagnostics.argtypes = [P, D]
         L.orc_lattice.argtypes = [I, D, I]
         L.orc_equilibrium.argtypes = [ctypes.c_double, D, D]
+        L.orc_equilibrium_stress.argtypes = [ctypes.c_double, D, D, D]
         L.orc_source.argtypes = [D, D, D]
         L.orc_collide_node.argtypes = [D, ctypes.c_double, D, D, ctypes.c_double, D]
         L.orc_fenep_kinematic.argtypes = [P, D, ctypes.c_long]
@@ -113,6 +115,16 @@ def equilibrium(rho: float, u) -> np.ndarray:
     return E
 
 
+
+def equilibrium_stress(rho: float, u, Ts) -> np.ndarray:
+    """Equilibrium whose second moment is lowered by the symmetric tensor Ts (xx, yy, zz,
+    xy, xz, yz): the stress coupling of Sec. 2, eq. MODEtransformation."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    Ts = np.ascontiguousarray(Ts, dtype=np.float64)
+    E = np.zeros(19)
+    lib().orc_equilibrium_stress(float(rho), _dp(u), _dp(Ts), _dp(E))
+    return E
+
 def source(u, F) -> np.ndarray:
     u = np.ascontiguousarray(u, dtype=np.float64)
     F = np.ascontiguousarray(F, dtype=np.float64)
@@ -151,9 +163,10 @@ class Oracle:
             self._h = None
 
     def set_params(self, tau_A=1.0, tau_B=1.0, G=0.0, delta=0.1, polymer_phase="none",
-                   eta_p=0.0, tau_p=1000.0, L2=100.0):
+                   eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force"):
         ph = PHASE[polymer_phase] if isinstance(polymer_phase, str) else int(polymer_phase)
-        lib().orc_set_params(self._h, tau_A, tau_B, G, delta, ph, eta_p, tau_p, L2)
+        cp = COUPLING[coupling] if isinstance(coupling, str) else int(coupling)
+        lib().orc_set_params(self._h, tau_A, tau_B, G, delta, ph, eta_p, tau_p, L2, cp)
 
     def set_walls(self, u_bottom, u_top):
         ub = np.ascontiguousarray(u_bottom, dtype=np.float64)
@@ -218,7 +231,7 @@ def from_workload(wl) -> Oracle:
     p = wl["params"]
     o.set_params(tau_A=p["tau_A"], tau_B=p["tau_B"], G=p["G"], delta=p["delta"],
                  polymer_phase=p["polymer_phase"], eta_p=p["eta_p"], tau_p=p["tau_p"],
-                 L2=p["L2"])
+                 L2=p["L2"], coupling=p.get("coupling", "force"))
     o.set_walls(wl["walls"]["u_bottom"], wl["walls"]["u_top"])
     o.set_fields(wl["rho"], wl["u"], wl["C"])
     return o

@@ -18,7 +18,9 @@
  *       f(r) = (L^2 - 3)/(L^2 - tr C), and its divergence by 2nd-order central
  *       differences F_p,j = sum_i d_i T_ij                          (Sec. 2, FENE-P feedback;
  *                                                                     modulated-feedback eq.)
- *   S5  force split F_s = g_s + (rho_s/rho) F_p (species weight of eq. MODEtransformation)
+ *   S5  force split F_s = g_s + (rho_s/rho) F_p (species weight of eq. MODEtransformation);
+ *       with the stress coupling instead F_s = g_s and T_s = (rho_s/rho) T lowers the
+ *       second moment of the equilibrium in S8 (eq. MODEtransformation)
  *   S6  velocity u = (j + sum_s F_s / 2)/rho                          (Sec. 2, eq. equilibrium:vel)
  *   S7  local BGK time tau = tau_B + (tau_A - tau_B) f+(phi)
  *   S8  BGK collision with the equilibrium and source of Sec. 2 (eq. LB with Lambda = I/tau)
@@ -69,11 +71,17 @@ static double W(int a) { return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 
 #define ORC_PHASE_B 2
 #define ORC_PHASE_ALL 3
 
+/* how the polymer stress reaches the fluid */
+#define ORC_COUPLING_FORCE 0  /* body force F_p = div T, split by rho_s/rho (Sec. 2, eq. NS) */
+#define ORC_COUPLING_STRESS 1 /* T_s = (rho_s/rho) T subtracted from the equilibrium's second
+                                 moment (Sec. 2, eq. MODEtransformation) */
+
 typedef struct {
     int nx, ny, nz, nc;
     long N;
     double tauA, tauB, G, delta, eta_p, tau_p, L2;
     int phase;
+    int coupling;
     double ub[3], ut[3];
     double *f, *fn;   /* [nc][19][N] */
     double *C, *Cn;   /* [6][N]      */
@@ -134,9 +142,9 @@ void orc_destroy(orc_t *o) {
 }
 
 void orc_set_params(orc_t *o, double tauA, double tauB, double G, double delta, int phase,
-                    double eta_p, double tau_p, double L2) {
+                    double eta_p, double tau_p, double L2, int coupling) {
     o->tauA = tauA; o->tauB = tauB; o->G = G; o->delta = delta; o->phase = phase;
-    o->eta_p = eta_p; o->tau_p = tau_p; o->L2 = L2;
+    o->eta_p = eta_p; o->tau_p = tau_p; o->L2 = L2; o->coupling = coupling;
 }
 
 void orc_set_walls(orc_t *o, const double ub[3], const double ut[3]) {
@@ -161,6 +169,19 @@ static double source(int a, const double u[3], const double F[3]) {
     double s = 0.0;
     for (int d = 0; d < 3; d++) s += (3.0 * (c[d] - u[d]) + 9.0 * cu * c[d]) * F[d];
     return W(a) * s;
+}
+
+/* Polymer stress in the equilibrium (Sec. 2, eq. MODEtransformation): the second moment of
+ * the equilibrium of species s is lowered by T_s.  With Q_a = c_a c_a - cs2 I the
+ * D3Q19 fourth-order isotropy gives sum_a w_a c_a c_a (Q_a : T) = 2 cs2^2 T, so the term
+ * -w_a Q_a : T_s / (2 cs2^2) = -4.5 w_a (c_a . T_s . c_a - tr T_s / 3) does exactly that and
+ * leaves the zeroth and first moments unchanged.  T_s in (xx, yy, zz, xy, xz, yz) order. */
+static double equilibrium_stress_term(int a, const double Ts[6]) {
+    double c[3] = {CX[a], CY[a], CZ[a]};
+    double cTc = c[0] * c[0] * Ts[0] + c[1] * c[1] * Ts[1] + c[2] * c[2] * Ts[2] +
+                 2.0 * (c[0] * c[1] * Ts[3] + c[0] * c[2] * Ts[4] + c[1] * c[2] * Ts[5]);
+    double tr = Ts[0] + Ts[1] + Ts[2];
+    return -4.5 * W(a) * (cTc - tr / 3.0);
 }
 
 static double fplus(const orc_t *o, double phi) { return 0.5 * (1.0 + tanh(phi / o->delta)); }
@@ -321,7 +342,7 @@ static void s5_s6_force_velocity(orc_t *o) {
         for (int s = 0; s < o->nc; s++) rho += o->rho[(long)s * N + n];
         double Ft[3] = {0, 0, 0};
         for (int s = 0; s < o->nc; s++) {
-            double share = o->rho[(long)s * N + n] / rho;
+            double share = o->coupling == ORC_COUPLING_FORCE ? o->rho[(long)s * N + n] / rho : 0.0;
             for (int d = 0; d < 3; d++) {
                 double Fs = o->g[((long)s * 3 + d) * N + n] + share * o->Fp[d * N + n];
                 o->F[((long)s * 3 + d) * N + n] = Fs;
@@ -350,14 +371,22 @@ static void s8_s9_collide_stream(orc_t *o) {
                 long n = IDX(o, x, y, z);
                 double u[3] = {o->u[n], o->u[N + n], o->u[2 * N + n]};
                 double tau = o->tau[n];
+                double T[6] = {0, 0, 0, 0, 0, 0}, rho = 0.0;
+                if (o->coupling == ORC_COUPLING_STRESS) {
+                    int bad = 0;
+                    stress_at(o, x, y, z, T, &bad);
+                    for (int s = 0; s < o->nc; s++) rho += o->rho[(long)s * N + n];
+                }
                 for (int s = 0; s < o->nc; s++) {
                     double rs = o->rho[(long)s * N + n];
                     double F[3] = {o->F[((long)s * 3) * N + n], o->F[((long)s * 3 + 1) * N + n],
                                    o->F[((long)s * 3 + 2) * N + n]};
+                    double Ts[6];
+                    for (int k = 0; k < 6; k++) Ts[k] = o->coupling == ORC_COUPLING_STRESS ? rs / rho * T[k] : 0.0;
                     for (int a = 0; a < NQ; a++) {
                         double fa = o->f[((long)s * NQ + a) * N + n];
-                        double post = fa - (fa - equilibrium(a, rs, u)) / tau +
-                                      (1.0 - 0.5 / tau) * source(a, u, F);
+                        double Ea = equilibrium(a, rs, u) + equilibrium_stress_term(a, Ts);
+                        double post = fa - (fa - Ea) / tau + (1.0 - 0.5 / tau) * source(a, u, F);
                         int yd = y + CY[a];
                         if (yd >= 0 && yd < o->ny) {
                             long nd = IDX(o, wrap(x + CX[a], o->nx), yd, wrap(z + CZ[a], o->nz));
@@ -605,6 +634,11 @@ void orc_lattice(int *c, double *w, int *opp) {
 
 void orc_equilibrium(double rho, const double *u, double *E) {
     for (int a = 0; a < NQ; a++) E[a] = equilibrium(a, rho, u);
+}
+
+/* Equilibrium with the polymer stress T_s in its second moment (single node). */
+void orc_equilibrium_stress(double rho, const double *u, const double *Ts, double *E) {
+    for (int a = 0; a < NQ; a++) E[a] = equilibrium(a, rho, u) + equilibrium_stress_term(a, Ts);
 }
 
 void orc_source(const double *u, const double *F, double *S) {

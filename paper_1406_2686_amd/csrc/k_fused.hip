@@ -288,7 +288,7 @@ __device__ __forceinline__ void phase_b(const DevParams& p, FusedTile<NC, TX, TY
         }
     }
     float Fp[3] = {0.f, 0.f, 0.f};
-    if (p.pstress != 0.0f) {
+    if (p.pstress != 0.0f && p.coupling == 0) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const int slp = i == 2 ? sn : sr;
@@ -445,6 +445,18 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
             const float cfac = 1.0f - 0.5f * om;
             const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
             const float b = -1.5f * uu;
+            // stress coupling (eq. MODEtransformation): T_s = (rho_s/rho) T lowers the second
+            // moment of this species' equilibrium by -4.5 w (c.T_s.c - tr T_s/3) per direction
+            const bool stress_eq = p.coupling == 1 && p.pstress != 0.0f;
+            float Ts[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (stress_eq) {
+                const float rtot = p.rho0[0] + L.rho[sr][0][oi2] + (NC == 2 ? p.rho0[1] + L.rho[sr][NC - 1][oi2] : 0.0f);
+                const float share = rs / rtot;
+                const float sv = share * L.cs[sr][6][oi2], s1v = share * L.cs[sr][7][oi2];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) Ts[k] = sv * L.cs[sr][k][oi2] + (k < 3 ? s1v : 0.0f);
+            }
+            const float trs3 = (Ts[0] + Ts[1] + Ts[2]) * (1.0f / 3.0f);
             const uint32_t zrow[3] = {(uint32_t)(r == 0 ? nz - 1 : r - 1) * plane, (uint32_t)r * plane,
                                       (uint32_t)(r + 1 == nz ? 0 : r + 1) * plane};
             const uint32_t bself = (zrow[1] + yrow + xcol[1]) * 4u;
@@ -452,7 +464,8 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
             {
                 const float w = wgt(0);
                 const float ha = L.pop[p2][comp][0][nid];
-                const float post = ha - om * (ha - w * (drs + rs * b)) + cfac * (w * (-3.0f * uF));
+                const float heq0 = w * (drs + rs * b) + (stress_eq ? 4.5f * w * trs3 : 0.0f);
+                const float post = ha - om * (ha - heq0) + cfac * (w * (-3.0f * uF));
                 st_off(hns, bself, post);
                 check = post;
             }
@@ -461,7 +474,14 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 const float w = wgt(a);
                 const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
                 const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
-                const float ee = w * (drs + rs * (4.5f * cu * cu + b));  // equilibrium, even part
+                float ee = w * (drs + rs * (4.5f * cu * cu + b));  // equilibrium, even part
+                if (stress_eq) {
+                    const float cTc = float(cx(a) * cx(a)) * Ts[0] + float(cy(a) * cy(a)) * Ts[1] +
+                                      float(cz(a) * cz(a)) * Ts[2] +
+                                      2.0f * (float(cx(a) * cy(a)) * Ts[3] + float(cx(a) * cz(a)) * Ts[4] +
+                                              float(cy(a) * cz(a)) * Ts[5]);
+                    ee -= 4.5f * w * (cTc - trs3);
+                }
                 const float eo = (3.0f * w) * rs * cu;                   // equilibrium, odd part
                 const float se = w * (9.0f * cu * cF - 3.0f * uF);       // source, even part
                 const float so = (3.0f * w) * cF;                        // source, odd part

@@ -177,6 +177,9 @@ __global__ __launch_bounds__(kBlock) void k_forces(DevParams p, const float* __r
         }
     }
 
+    // with the stress coupling the polymer acts through the equilibrium, not as a force (the
+    // stresses above are still evaluated for the fault checks)
+    if (p.coupling != 0) Fp[0] = Fp[1] = Fp[2] = 0.0f;
     const float inv_rho = 1.0f / rho;
     const float shA = rA * inv_rho, shB = rB * inv_rho;
     float FA[3], FB[3], u[3];
@@ -229,6 +232,16 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
     }
     const float om = 1.0f / tau;
     const float cf = 1.0f - 0.5f * om;
+    // stress coupling (eq. MODEtransformation): T at this node, shared by rho_s/rho below
+    float T[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const bool stress_eq = p.coupling == 1 && p.pstress != 0.0f;
+    if (stress_eq) {
+        float dv[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dv[k] = D[k * N + n];
+        unsigned bad_own = 0u;
+        stress(p, dv, phase_phi(p, rA, rB), T, bad_own);
+    }
 
     // destination row offsets (push streaming); -1 marks a link that leaves through a wall
     const int xp = wrap1(x + 1, nx), xm = wrap1(x - 1, nx);
@@ -242,12 +255,24 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
         const float drs = dr[s];
         const float F[3] = {uF[(3 + 3 * s) * N + n], uF[(4 + 3 * s) * N + n], uF[(5 + 3 * s) * N + n]};
         const float uFd = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+        const float share = rs / (rA + rB);
+        float Ts[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Ts[k] = share * T[k];
+        const float trs3 = (Ts[0] + Ts[1] + Ts[2]) * (1.0f / 3.0f);
 #pragma unroll
         for (int a = 0; a < kQ; ++a) {
             const float ha = hs[a * N + n];
             const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
             const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
-            const float heq = wgt(a) * (drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+            float heq = wgt(a) * (drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+            if (stress_eq) {
+                const float cTc = float(cx(a) * cx(a)) * Ts[0] + float(cy(a) * cy(a)) * Ts[1] +
+                                  float(cz(a) * cz(a)) * Ts[2] +
+                                  2.0f * (float(cx(a) * cy(a)) * Ts[3] + float(cx(a) * cz(a)) * Ts[4] +
+                                          float(cy(a) * cz(a)) * Ts[5]);
+                heq -= 4.5f * wgt(a) * (cTc - trs3);
+            }
             const float src = wgt(a) * (3.0f * (cF - uFd) + 9.0f * cu * cF);
             const float post = ha - om * (ha - heq) + cf * src;
             check += post;

@@ -75,6 +75,7 @@ const char* params_problem(const lbfd_params* p) {
     if (!(p->L2 > 3.0)) return "L2 must exceed 3";
     if (p->eta_p < 0.0) return "eta_p must be non-negative";
     if (p->polymer_phase < LBFD_POLYMER_NONE || p->polymer_phase > LBFD_POLYMER_ALL) return "bad polymer_phase";
+    if (p->coupling != LBFD_COUPLING_FORCE && p->coupling != LBFD_COUPLING_STRESS) return "bad coupling";
     return nullptr;
 }
 
@@ -97,6 +98,8 @@ void fill_devparams(lbfd_ctx* c) {
     d.inv_tau_p = (float)(1.0 / p.tau_p);
     d.L2 = (float)p.L2;
     d.L2m3 = (float)(p.L2 - 3.0);
+    d.coupling = p.coupling;
+    d.pad_ = 0;
     for (int k = 0; k < 3; ++k) {
         d.ub[k] = (float)c->ub[k];
         d.ut[k] = (float)c->ut[k];

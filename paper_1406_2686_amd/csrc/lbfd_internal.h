@@ -20,6 +20,8 @@ struct DevParams {
     float L2;          // L^2
     float L2m3;        // L^2 - 3
     float ub[3], ut[3];
+    int coupling;      // LBFD_COUPLING_* (0: body force, 1: stress in the equilibrium)
+    int pad_;
 };
 
 // Views into the caller-owned device buffer.

@@ -14,22 +14,24 @@ from paper_closed_forms import cessation_S_ratio, lindner_N, lindner_S, steady_s
 KEYS = ("xx", "yy", "zz", "xy", "xz", "yz")
 
 
-def couette(ny, U, tau_p, L2, eta_p, nx=2, nz=2):
-    wl = workloads.couette_fenep(nx=nx, ny=ny, nz=nz, U=U, tau_p=tau_p, L2=L2, noise=0.0)
+def couette(ny, U, tau_p, L2, eta_p, nx=2, nz=2, coupling="force"):
+    wl = workloads.couette_fenep(nx=nx, ny=ny, nz=nz, U=U, tau_p=tau_p, L2=L2, noise=0.0,
+                                 coupling=coupling)
     wl["params"]["eta_p"] = eta_p
     return oracle.from_workload(wl), wl
 
 
-@pytest.mark.parametrize("Lam,L2,tau_p", [(0.625, 100.0, 1000.0), (2.5, 100.0, 200.0),
-                                          (0.625, 1e8, 200.0)])
-def test_steady_shear_matches_lindner(Lam, L2, tau_p):
+@pytest.mark.parametrize("Lam,L2,tau_p,coupling", [(0.625, 100.0, 1000.0, "force"), (2.5, 100.0, 200.0, "force"),
+                                                   (0.625, 1e8, 200.0, "force"), (2.5, 100.0, 200.0, "stress")])
+def test_steady_shear_matches_lindner(Lam, L2, tau_p, coupling):
     """Full LB+FD run of plane Couette with feedback on; after 20 polymer times the
     conformation tensor equals the closed-form steady shear solution C = sigma_P/Z
-    (eqs. EQNS, N2S, cubic, lindner, lindner2)."""
+    (eqs. EQNS, N2S, cubic, lindner, lindner2), with the stress acting as a body force or
+    through the equilibrium (eq. MODEtransformation): a uniform stress moves no fluid."""
     ny = 16
     gdot = Lam / tau_p
     U = gdot * ny / 2.0
-    o, wl = couette(ny, U, tau_p, L2, eta_p=1.0 / 24.0)
+    o, wl = couette(ny, U, tau_p, L2, eta_p=1.0 / 24.0, coupling=coupling)
     assert o.step(int(20 * tau_p)) == 0
     _, u, C = o.get_fields()
     ref = steady_shear_conformation(Lam, L2)

@@ -59,6 +59,28 @@ def test_equilibrium_moments(seed):
 
 
 @pytest.mark.parametrize("seed", range(5))
+def test_equilibrium_with_stress_moments(seed):
+    """Stress coupling (Sec. 2, eq. MODEtransformation): the equilibrium keeps rho and
+    rho u and its second moment is lowered by exactly the given symmetric tensor T_s."""
+    c, _, _ = oracle.lattice()
+    rng = np.random.default_rng(200 + seed)
+    rho = rng.uniform(0.02, 2.5)
+    u = rng.uniform(-0.1, 0.1, 3)
+    A = rng.uniform(-1e-2, 1e-2, (3, 3))
+    T = A + A.T
+    Ts = np.array([T[0, 0], T[1, 1], T[2, 2], T[0, 1], T[0, 2], T[1, 2]])
+    E = oracle.equilibrium_stress(rho, u, Ts)
+    assert abs(E.sum() - rho) < 1e-14 * rho
+    assert np.allclose(E @ c, rho * u, atol=1e-15)
+    P = np.einsum("a,ai,aj->ij", E, c, c)
+    assert np.allclose(P, rho * (np.outer(u, u) + np.eye(3) / 3.0) - T, atol=1e-14)
+    # an isotropic stress shifts only the pressure: P = rho (uu + I/3) - t I
+    E = oracle.equilibrium_stress(rho, u, [0.01, 0.01, 0.01, 0, 0, 0])
+    P = np.einsum("a,ai,aj->ij", E, c, c)
+    assert np.allclose(P, rho * (np.outer(u, u) + np.eye(3) / 3.0) - 0.01 * np.eye(3), atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(5))
 def test_source_moments(seed):
     """Sum S = 0, sum c S = F, sum c c S = u F + F u (second-order forcing)."""
     c, _, _ = oracle.lattice()

@@ -334,3 +334,37 @@ def test_upwind_advection_translates_and_stays_monotone():
             cen1 = (X * ex).sum() / ex.sum()
             assert abs(cen1 - cen0 - ux * steps) < 1e-9
             assert ex.max() <= (C[k] - (k == 0)).max() + 1e-15 and ex.min() >= -1e-15
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8, 1.7])
+def test_stress_coupling_first_step_closed_form(tau):
+    """Stress coupling (Sec. 2, eq. MODEtransformation) from rest: one component at uniform
+    density, C = I + a sin(k z) (e_x e_z + e_z e_x), so tr C = 3, f(r) = 1 and
+    T_xz = (eta_p/tau_p) a sin(k z).  The collision moves the populations by
+    -(9/tau) w c_x c_z T_xz toward the lowered equilibrium; streaming over the four
+    (+-1, 0, +-1) links then gives exactly j_x(z) = (eta_p/tau_p) a sin(k) cos(k z) / tau,
+    the central divergence of T divided by tau, with rho unchanged.  With the body-force
+    coupling the same field gives the force (eta_p/tau_p) a sin(k) cos(k z) instead."""
+    nx, ny, nz = 4, 5, 24
+    k = 2 * np.pi / nz
+    a, eta_p, tau_p = 0.1, 0.02, 50.0
+    wl = workloads.couette_fenep(nx=nx, ny=ny, nz=nz, U=0.0, tau=tau, tau_p=tau_p, L2=100.0,
+                                 noise=0.0, coupling="stress")
+    wl["params"]["eta_p"] = eta_p
+    N = nx * ny * nz
+    Z = np.repeat(np.arange(nz), nx * ny)
+    wl["u"] = np.zeros((3, N))
+    wl["rho"] = np.ones((1, N))
+    wl["C"][4] = a * np.sin(k * Z)
+    o = oracle.from_workload(wl)
+    assert o.step(1) == 0
+    rho, u, _ = o.get_fields()
+    expect = eta_p / tau_p * a * np.sin(k) * np.cos(k * Z) / tau
+    assert np.allclose(rho[0], 1.0, rtol=0, atol=1e-15)
+    assert np.allclose(u[0], expect, rtol=0, atol=1e-15)
+    assert np.max(np.abs(u[1:])) < 1e-15
+    # the body-force coupling sees the same divergence as a force
+    wl["params"]["coupling"] = "force"
+    o = oracle.from_workload(wl)
+    _, Fp, _ = o.get_forces()
+    assert np.allclose(Fp[0], eta_p / tau_p * a * np.sin(k) * np.cos(k * Z), rtol=0, atol=1e-16)

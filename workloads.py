@@ -10,7 +10,8 @@ Every workload is a dict::
     {"name": str,
      "grid":   {"nx", "ny", "nz", "ncomp"},              # y is the wall-normal axis
      "params": {"tau_A", "tau_B", "G", "delta", "rho0": [r0A, r0B],
-                "polymer_phase": "none"|"A"|"B"|"all", "eta_p", "tau_p", "L2"},
+                "polymer_phase": "none"|"A"|"B"|"all", "eta_p", "tau_p", "L2",
+                "coupling": "force"|"stress"},
      "walls":  {"u_bottom": [ux, 0, uz], "u_top": [ux, 0, uz]},
      "rho": (ncomp, N) f64, "u": (3, N) f64, "C": (6, N) f64}
 
@@ -75,7 +76,7 @@ def couette_profile(y, ny, U):
 
 
 def couette_fenep(nx=16, ny=32, nz=16, seed=0, U=0.01, tau=1.0, tau_p=1000.0, L2=100.0,
-                  beta=0.2, noise=1e-3):
+                  beta=0.2, noise=1e-3, coupling="force"):
     N = nx * ny * nz
     eta_s = (tau - 0.5) * CS2
     eta_p = eta_s * beta / (1.0 - beta)
@@ -97,7 +98,8 @@ def couette_fenep(nx=16, ny=32, nz=16, seed=0, U=0.01, tau=1.0, tau_p=1000.0, L2
         "name": f"couette_fenep_{nx}x{ny}x{nz}",
         "grid": _grid(nx, ny, nz, 1),
         "params": {"tau_A": tau, "tau_B": tau, "G": 0.0, "delta": 0.1, "rho0": [1.0, 0.0],
-                   "polymer_phase": "all", "eta_p": eta_p, "tau_p": tau_p, "L2": L2},
+                   "polymer_phase": "all", "eta_p": eta_p, "tau_p": tau_p, "L2": L2,
+                   "coupling": coupling},
         "walls": {"u_bottom": [-U, 0.0, 0.0], "u_top": [U, 0.0, 0.0]},
         "rho": rho, "u": u, "C": C,
         "meta": {"U": U, "gdot": 2 * U / ny, "eta_s": eta_s, "Lambda": tau_p * 2 * U / ny},
@@ -130,7 +132,7 @@ def droplet_fields(nx, ny, nz, R, rho_in, rho_out, U, box=None):
 
 def droplet_shear(nx=128, ny=64, nz=128, R=16.0, rho_in=1.0, rho_out=0.04, G=0.9,
                   tau_A=1.0, tau_B=1.0, polymer_phase="A", L2=100.0, De=1.0, Ca=0.2,
-                  concentration=0.4, sigma=None, U=None, box=None, name=None):
+                  concentration=0.4, sigma=None, U=None, box=None, name=None, coupling="force"):
     """Droplet-in-shear workload.  ``sigma`` (interfacial tension) sets U from Ca unless
     ``U`` is given; ``concentration`` = eta_p/(eta_s + eta_p) of the viscoelastic phase."""
     rho_tot = rho_in + rho_out
@@ -158,7 +160,8 @@ def droplet_shear(nx=128, ny=64, nz=128, R=16.0, rho_in=1.0, rho_out=0.04, G=0.9
         "name": name or f"droplet_shear_{nx}x{ny}x{nz}_R{R:g}",
         "grid": g,
         "params": {"tau_A": tau_A, "tau_B": tau_B, "G": G, "delta": 0.1, "rho0": [r0A, r0B],
-                   "polymer_phase": polymer_phase, "eta_p": eta_p, "tau_p": tau_p, "L2": L2},
+                   "polymer_phase": polymer_phase, "eta_p": eta_p, "tau_p": tau_p, "L2": L2,
+                   "coupling": coupling},
         "walls": {"u_bottom": [-U, 0.0, 0.0], "u_top": [U, 0.0, 0.0]},
         "rho": rho, "u": u, "C": C,
         "meta": {"U": U, "gdot": 2 * U / ny, "eta_M": eta_M, "sigma": sigma, "Ca": Ca,
