@@ -189,6 +189,86 @@ def sweep(lb, workloads, args):
     print(json.dumps(out), flush=True)
 
 
+def batch_bench(lb, workloads, args):
+    """Throughput of the batched step (one launch per step over every instance, replayed
+    from the captured two-launch graph) on the droplet sweep family."""
+    import torch
+
+    cases = workloads.sweep_cases(args.batch, seed=4001, scale=args.scale)
+    wls = [workloads.sweep_workload(c) for c in cases]
+    # instances whose explicit polymer feedback goes unstable (fault flags) within the run
+    # are screened out first: a faulting instance stops a plain batched step
+    horizon = args.warmup + args.warmup % 2 + args.steps + args.steps % 2
+    screen = lb.Batch(wls)
+    _, ss = screen.run_to_steady(every=50, window=50 * (horizon // 50 + 2), tol=1e-300, max_steps=horizon + 50)
+    screen.close()
+    dropped = [i for i, s in enumerate(ss) if s == -2]
+    wls = [w for i, w in enumerate(wls) if i not in dropped]
+    nodes = sum(w["grid"]["nx"] * w["grid"]["ny"] * w["grid"]["nz"] for w in wls)
+    b = lb.Batch(wls)
+    b.step(args.warmup + args.warmup % 2)
+    torch.cuda.synchronize()
+    K = args.steps + args.steps % 2
+    a = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    a.record(b.stream)
+    b.step(K)
+    e.record(b.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = a.elapsed_time(e) / K
+    achieved = ALG_BYTES[2] * nodes / (ms * 1e-3) / 1e9
+    d = b.diagnostics()
+    b.close()
+    print(json.dumps({"metric": "batched step throughput (droplet sweep family)", "value": round(nodes * K / wall / 1e6, 1),
+                      "unit": "MLUPS", "n_gpus": 1, "steps": K, "ms_per_step": round(ms, 4), "dtype": "f32",
+                      "data": "synthetic", "higher_is_better": True,
+                      "config": {"workload": f"{len(wls)} droplet-in-shear lattices, grids x{args.scale} of 64-192 x 32-64",
+                                 "nodes": nodes, "faulting_instances_dropped": dropped},
+                      "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                                   "kernel": "k_fused_batch (all instances, one launch per step)"},
+                      "fault_flags": int(max(x["flags"] for x in d))}), flush=True)
+
+
+def mlp_bench(lb, workloads, args):
+    """The surrogate network's kernels: BF16 inference on the matrix cores, FP32 forward,
+    and on-device training (forward, backward, Adam per minibatch)."""
+    import numpy as np
+    import torch
+
+    net = lb.MLP(max_batch=512, max_train=4096, seed=1)
+    X, T = workloads.mlp_batch(4096, seed=5)
+    Xi = X[:512]
+    for _ in range(5):
+        net.infer_bf16(Xi)
+    reps = 200
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.infer_bf16(Xi)
+    t_inf = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(Xi)
+    t_fwd = (time.perf_counter() - t0) / reps
+    epochs, batch = 50, 256
+    t0 = time.perf_counter()
+    loss = net.train(X, T, epochs=epochs, batch=batch, lr=2e-3, seed=3)
+    t_train = time.perf_counter() - t0
+    steps = epochs * (len(X) // batch)
+    flop = 2 * (5 * 128 + 128 * 128 + 128 * 3)
+    net.close()
+    print(json.dumps({"metric": "surrogate network (5-128-128-3) kernels", "unit": "samples/s",
+                      "value": round(512 / t_inf, 1), "n_gpus": 1, "dtype": "bf16 inference, f32 training",
+                      "data": "synthetic", "higher_is_better": True,
+                      "config": {"workload": "512-sample inference calls; 4096-sample training set, batch 256"},
+                      "infer_bf16_call_ms": round(t_inf * 1e3, 4), "forward_f32_call_ms": round(t_fwd * 1e3, 4),
+                      "train_step_ms": round(t_train / steps * 1e3, 4), "train_steps": steps,
+                      "final_loss": loss, "flop_per_sample": flop}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,11 +278,14 @@ def main():
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
-                    help="droplet-sweep mode: plain vs batched vs surrogate-warm-started time to steady D")
+                    help="droplet-sweep mode: plain vs batched vs surrogate (with solver fallback) time to steady D")
     ap.add_argument("--n-train", type=int, default=2048)
     ap.add_argument("--n-test", type=int, default=256)
     ap.add_argument("--scale", type=float, default=0.5)
     ap.add_argument("--max-steps", type=int, default=12000)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="time the batched step over this many sweep lattices instead")
+    ap.add_argument("--mlp", action="store_true", help="time the surrogate network's kernels instead")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM calibration)")
     args = ap.parse_args()
@@ -222,6 +305,12 @@ def main():
         return
     if args.sweep:
         sweep(lb, workloads, args)
+        return
+    if args.batch > 0:
+        batch_bench(lb, workloads, args)
+        return
+    if args.mlp:
+        mlp_bench(lb, workloads, args)
         return
 
     nx, ny, nz = (int(v) for v in args.grid.split("x"))

@@ -161,12 +161,16 @@ lbfd_status lbfd_get_state(lbfd_ctx* ctx, void* host, uint64_t bytes);
 lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
 
 /* Launch shape of the step.  path: LBFD_PATH_FUSED (one pass over HBM per step, the
- * default) or LBFD_PATH_SPLIT (three passes: moments, forces, collide; same arithmetic,
- * kept as a cross-check).  tile: LBFD_TILE_32x8 / 32x16 / 16x16 (x by y nodes per
- * workgroup of the fused pass; 32x16 runs as 32x8).  zchunk: planes per workgroup along z, 0 = automatic.
- * Results are identical for every tile and zchunk; only speed changes. */
+ * default), LBFD_PATH_TWOPASS (a streaming moments pass, then one pass that reads the
+ * moments and C with their halos and only the tile's own populations) or LBFD_PATH_SPLIT
+ * (three passes: moments, forces, collide; kept as a cross-check).  The three paths compute
+ * the same step; their results agree to FP32 rounding.  tile: LBFD_TILE_32x8 / 32x16 /
+ * 16x16 (x by y nodes per workgroup of the fused and two-pass steps; 32x16 runs as 32x8).
+ * zchunk: planes per workgroup along z, 0 = automatic.  Within one path, results are
+ * identical for every tile and zchunk; only speed changes. */
 #define LBFD_PATH_FUSED 0
 #define LBFD_PATH_SPLIT 1
+#define LBFD_PATH_TWOPASS 2
 #define LBFD_TILE_32x8 0
 #define LBFD_TILE_32x16 1
 #define LBFD_TILE_16x16 2

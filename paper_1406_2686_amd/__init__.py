@@ -74,7 +74,7 @@ class Tuning(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
-PATH_FUSED, PATH_SPLIT = 0, 1
+PATH_FUSED, PATH_SPLIT, PATH_TWOPASS = 0, 1, 2
 TILES = {"32x8": 0, "32x16": 1, "16x16": 2}
 
 _P = ctypes.c_void_p

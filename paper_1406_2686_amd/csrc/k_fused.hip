@@ -115,7 +115,9 @@ __device__ __forceinline__ void halo1_pos(int k, int& lx, int& ly) {
 
 }  // namespace
 
-template <int NC, int TX, int TY>
+// LDS of one workgroup.  TP (two-pass step): the moments come from a preceding pass, so
+// the per-component momenta and the ring of own populations are not needed (size 1).
+template <int NC, int TX, int TY, bool TP>
 struct FusedTile {
     static constexpr int NT = TX * TY;    // nodes per tile
     static constexpr int NTH = NC * NT;   // threads: one per (node, component)
@@ -126,10 +128,10 @@ struct FusedTile {
     float rho[3][NC][A2];       // delta rho per component (ring over planes)
     float cs[3][8][A2];         // D = C - I (6), s, s1 (ring over planes)
     float u[3][3][A1];          // total j (after A2), u (after B) (ring over planes)
-    float jc[NC][3][A1];        // momentum per component of the entering plane
     float Fo[NC][3][NT];        // species forces of the tile nodes, phase B -> C
     float fpl[2][NT];           // f+(phi) of the tile nodes, planes q and q-1
-    float pop[2][NC][kQ][NT];   // own populations, planes q and q-1
+    float jc[TP ? 1 : NC][3][TP ? 1 : A1];                  // momentum per component
+    float pop[TP ? 1 : 2][TP ? 1 : NC][kQ][TP ? 1 : NT];     // own populations, planes q, q-1
 };
 
 // Populations of one component and (optionally) D of one node, as loaded.
@@ -164,9 +166,9 @@ __device__ __forceinline__ void issue_load(const float* __restrict__ hs, const f
 // later).  Positions beyond a wall hold the wall layer's values (densities copy the wall
 // layer; C and the stress are replaced in phase A2).
 template <int NC, int TX, int TY, bool OWN>
-__device__ __forceinline__ void phase_a1(FusedTile<NC, TX, TY>& L, int sq, int s2, int c, int nid, int lx, int ly,
+__device__ __forceinline__ void phase_a1(FusedTile<NC, TX, TY, false>& L, int sq, int s2, int c, int nid, int lx, int ly,
                                          bool with_d, const NodeLoad& v) {
-    using T = FusedTile<NC, TX, TY>;
+    using T = FusedTile<NC, TX, TY, false>;
     float sum = v.f[0];
 #pragma unroll
     for (int a = 1; a < kQ; a += 2) sum += v.f[a] + v.f[a + 1];
@@ -200,10 +202,10 @@ __device__ __forceinline__ void phase_a1(FusedTile<NC, TX, TY>& L, int sq, int s
 // two wall-adjacent layers, Sec. 2 boundary condition of C), f+(phi), the stress
 // coefficients s = (eta_p/tau_p) m(phi) f(r), s1 = (eta_p/tau_p) m(phi) (f(r) - 1), and the
 // total momentum.
-template <int NC, int TX, int TY>
-__device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, TY>& L, int sq, int s2, int y0, int k,
+template <int NC, int TX, int TY, bool TP>
+__device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, TY, TP>& L, int sq, int s2, int y0, int k,
                                          unsigned& bad) {
-    using T = FusedTile<NC, TX, TY>;
+    using T = FusedTile<NC, TX, TY, TP>;
     const int lx = k % T::W2 - 2, ly = k / T::W2 - 2;
     const int gy = y0 + ly;
     const int i2 = k;
@@ -244,7 +246,7 @@ __device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, T
     L.cs[sq][6][i2] = pm * p.L2m3 * inv;
     L.cs[sq][7][i2] = pm * trd * inv;
     if (NC == 2 && lx >= 0 && lx < TX && ly >= 0 && ly < TY) L.fpl[s2][ly * TX + lx] = 0.5f * (1.0f + th);
-    if (lx >= -1 && lx <= TX && ly >= -1 && ly <= TY) {
+    if (!TP && lx >= -1 && lx <= TX && ly >= -1 && ly <= TY) {
         const int i1 = (ly + 1) * T::W1 + lx + 1;
 #pragma unroll
         for (int d = 0; d < 3; ++d) L.u[sq][d][i1] = NC == 2 ? L.jc[0][d][i1] + L.jc[NC - 1][d][i1] : L.jc[0][d][i1];
@@ -253,10 +255,10 @@ __device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, T
 
 // Phase B for one in-domain node of plane q-1 at local (lx, ly): Shan-Chen force, polymer
 // stress divergence, species forces and velocity; u replaces j in LDS slot sr.
-template <int NC, int TX, int TY>
-__device__ __forceinline__ void phase_b(const DevParams& p, FusedTile<NC, TX, TY>& L, int sp, int sr,
+template <int NC, int TX, int TY, bool TP>
+__device__ __forceinline__ void phase_b(const DevParams& p, FusedTile<NC, TX, TY, TP>& L, int sp, int sr,
                                         int sn, int lx, int ly, float (&Fs)[2][3]) {
-    using T = FusedTile<NC, TX, TY>;
+    using T = FusedTile<NC, TX, TY, TP>;
     const int i2 = (ly + 2) * T::W2 + lx + 2;
     const int i1 = (ly + 1) * T::W1 + lx + 1;
     float rs[2];
@@ -319,13 +321,26 @@ __device__ __forceinline__ void phase_b(const DevParams& p, FusedTile<NC, TX, TY
     for (int d = 0; d < 3; ++d) L.u[sr][d][i1] = u[d];
 }
 
+// Moments and D of one position of the tile + 2-node halo, as loaded (two-pass step).
+template <int NC>
+struct MomLoad {
+    float r[NC];
+    float j[3];
+    float d[6];
+};
+
 // One workgroup's share of a step: tile [x0, x0+TX) x [y0, y0+TY), planes [z0, z1).
-template <int NC, int TX, int TY>
+// TP = false: single pass, the moments are formed here from the populations of the tile
+// and its halo.  TP = true: second pass of the two-pass step, delta rho and j of every
+// node come from `mom` (written by the moments pass over the same time level), so only the
+// tile's own populations are read, once, for the collision.
+template <int NC, int TX, int TY, bool TP>
 __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __restrict__ h,
                                            float* __restrict__ hn, const float* __restrict__ D,
                                            float* __restrict__ Dn, unsigned* __restrict__ flags,
-                                           FusedTile<NC, TX, TY>& L, int x0, int y0, int z0, int z1) {
-    using T = FusedTile<NC, TX, TY>;
+                                           FusedTile<NC, TX, TY, TP>& L, int x0, int y0, int z0, int z1,
+                                           const float* __restrict__ mom) {
+    using T = FusedTile<NC, TX, TY, TP>;
     static_assert(T::NH2 <= T::NT, "one R2 halo node per thread at most");
     static_assert(T::A1 <= 2 * T::NTH, "phase B covers the R1 region in two passes at most");
     static_assert(T::NT % 64 == 0, "a wavefront never straddles two components");
@@ -371,7 +386,41 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     // plane q+1 is loaded while plane q is processed; the loads land in the registers that
     // phase A1 has just emptied, so no copy (and no early wait) sits on the loop edge
     NodeLoad pf_own, pf_halo;
-    {
+    // two-pass: positions of the tile + halo this thread loads (moments and D), and the own
+    // populations of the plane collided next
+    constexpr int KP = (T::A2 + T::NTH - 1) / T::NTH;
+    MomLoad<NC> mpf[KP];
+    uint32_t mpos[KP];
+    float own_pop[kQ];
+    if (TP) {
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+            const int k = tid + i * T::NTH;
+            const int lx = k % T::W2 - 2, ly = k / T::W2 - 2;
+            const int gy = min(max(y0 + ly, 0), ny - 1);
+            mpos[i] = (uint32_t)gy * (uint32_t)nx + (uint32_t)wrapn(x0 + lx, nx);
+        }
+#pragma unroll
+        for (int a = 0; a < kQ; ++a) own_pop[a] = 0.0f;
+    }
+    auto issue_mom = [&](int zq) {
+        const uint32_t zoff = (uint32_t)wrapn(zq, nz) * plane;
+#pragma unroll
+        for (int i = 0; i < KP; ++i) {
+            if (tid + i * T::NTH < T::A2) {
+                const uint32_t bo = (zoff + mpos[i]) * 4u;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) mpf[i].r[c] = ld_off(mom + (size_t)c * N, bo);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) mpf[i].j[d] = ld_off(mom + (size_t)(NC + d) * N, bo);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) mpf[i].d[k] = ld_off(D + (size_t)k * N, bo);
+            }
+        }
+    };
+    if (TP) {
+        issue_mom(z0 - 2);
+    } else {
         const uint32_t zoff = (uint32_t)wrapn(z0 - 2, nz) * plane;
         issue_load(hs, D, N, zoff + own_xy, fene, pf_own);
         if (has_halo) issue_load(hs, D, N, zoff + halo_xy, halo_d, pf_halo);
@@ -383,17 +432,37 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
         const bool do_c = q >= z0 + 1 && q <= z1 && active;
 
         // ---------------- A1: consume plane q, then request plane q+1 ----------------
-        phase_a1<NC, TX, TY, true>(L, sq, s2, comp, nid, olx, oly, fene, pf_own);
-        if (has_halo) phase_a1<NC, TX, TY, false>(L, sq, s2, comp, nid, hlx, hly, halo_d, pf_halo);
-        if (q + 1 <= z1 + 1) {
-            const uint32_t zoff = (uint32_t)wrapn(q + 1, nz) * plane;
-            issue_load(hs, D, N, zoff + own_xy, fene, pf_own);
-            if (has_halo) issue_load(hs, D, N, zoff + halo_xy, halo_d, pf_halo);
+        if constexpr (TP) {
+#pragma unroll
+            for (int i = 0; i < KP; ++i) {
+                const int k = tid + i * T::NTH;
+                if (k < T::A2) {
+                    const int lx = k % T::W2 - 2, ly = k / T::W2 - 2;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) L.rho[sq][c][k] = mpf[i].r[c];
+#pragma unroll
+                    for (int kk = 0; kk < 6; ++kk) L.cs[sq][kk][k] = mpf[i].d[kk];
+                    if (lx >= -1 && lx <= TX && ly >= -1 && ly <= TY) {
+                        const int i1 = (ly + 1) * T::W1 + lx + 1;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) L.u[sq][d][i1] = mpf[i].j[d];
+                    }
+                }
+            }
+            if (q + 1 <= z1 + 1) issue_mom(q + 1);
+        } else {
+            phase_a1<NC, TX, TY, true>(L, sq, s2, comp, nid, olx, oly, fene, pf_own);
+            if (has_halo) phase_a1<NC, TX, TY, false>(L, sq, s2, comp, nid, hlx, hly, halo_d, pf_halo);
+            if (q + 1 <= z1 + 1) {
+                const uint32_t zoff = (uint32_t)wrapn(q + 1, nz) * plane;
+                issue_load(hs, D, N, zoff + own_xy, fene, pf_own);
+                if (has_halo) issue_load(hs, D, N, zoff + halo_xy, halo_d, pf_halo);
+            }
         }
         lds_barrier();
 
         // ---------------- A2: ghosts, f+, stress coefficients, total momentum ----------------
-        for (int k = tid; k < T::A2; k += T::NTH) phase_a2<NC, TX, TY>(p, L, sq, s2, y0, k, bad);
+        for (int k = tid; k < T::A2; k += T::NTH) phase_a2<NC, TX, TY, TP>(p, L, sq, s2, y0, k, bad);
         lds_barrier();
 
         // ---------------- B: forces and velocity on plane q-1 (tile + 1 halo) -------------
@@ -411,7 +480,7 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 const int gy = y0 + ly;
                 if (gy < 0 || gy >= ny) continue;  // ghost velocities come from the wall rule
                 float Fs[2][3];
-                phase_b<NC, TX, TY>(p, L, sp, sr, sq, lx, ly, Fs);
+                phase_b<NC, TX, TY, TP>(p, L, sp, sr, sq, lx, ly, Fs);
                 if (k < T::NT) {
 #pragma unroll
                     for (int s = 0; s < NC; ++s)
@@ -463,7 +532,7 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
             float check;
             {
                 const float w = wgt(0);
-                const float ha = L.pop[p2][comp][0][nid];
+                const float ha = TP ? own_pop[0] : L.pop[TP ? 0 : p2][TP ? 0 : comp][0][TP ? 0 : nid];
                 const float heq0 = w * (drs + rs * b) + (stress_eq ? 4.5f * w * trs3 : 0.0f);
                 const float post = ha - om * (ha - heq0) + cfac * (w * (-3.0f * uF));
                 st_off(hns, bself, post);
@@ -488,7 +557,7 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int bq = a + e;
-                    const float ha = L.pop[p2][comp][bq][nid];
+                    const float ha = TP ? own_pop[bq] : L.pop[TP ? 0 : p2][TP ? 0 : comp][bq][TP ? 0 : nid];
                     const float heq = e == 0 ? ee + eo : ee - eo;
                     const float src = e == 0 ? se + so : se - so;
                     const float post = ha - om * (ha - heq) + cfac * src;
@@ -506,6 +575,13 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 }
             }
             if (!isfinite(check)) bad |= 1u;
+        }
+        if (TP && q >= z0 && q < z1) {
+            // own populations of plane q, collided in the next iteration; the registers were
+            // emptied by phase C just above
+            const uint32_t bo = ((uint32_t)wrapn(q, nz) * plane + own_xy) * 4u;
+#pragma unroll
+            for (int a = 0; a < kQ; ++a) own_pop[a] = ld_off(hs + (size_t)a * N, bo);
         }
 
         // ---------------- D: FENE-P on plane q-2 (own node, component-0 threads) ----------
@@ -610,7 +686,7 @@ template <int NC, int TX, int TY>
 __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused(
     DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
     float* __restrict__ Dn, unsigned* __restrict__ flags, int zchunk) {
-    __shared__ FusedTile<NC, TX, TY> L;
+    __shared__ FusedTile<NC, TX, TY, false> L;
     const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
     // groups of about 256 x 32 nodes
     const int gxw = min(ntx, 256 / TX);
@@ -618,7 +694,26 @@ __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused(
     int tx_i, ty_i, zc_i;
     tile_of_block(blockIdx.x, gridDim.x, ntx, nty, gxw, gyh, tx_i, ty_i, zc_i);
     const int z0 = zc_i * zchunk;
-    fused_tile<NC, TX, TY>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0, min(z0 + zchunk, p.nz));
+    fused_tile<NC, TX, TY, false>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0, min(z0 + zchunk, p.nz),
+                                  nullptr);
+}
+
+// Second pass of the two-pass step: the moments of the whole lattice at time level n are
+// in `mom` (delta rho per component, then j), written by the moments pass.  Without the
+// population ring its LDS (72 KB for 32x8, two components) admits two workgroups per CU;
+// the launch bound asks for 4 waves per SIMD (128 VGPRs) so that both fit.
+template <int NC, int TX, int TY>
+__global__ __launch_bounds__(NC* TX* TY, 4) void k_fused2(
+    DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
+    float* __restrict__ Dn, const float* __restrict__ mom, unsigned* __restrict__ flags, int zchunk) {
+    __shared__ FusedTile<NC, TX, TY, true> L;
+    const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
+    const int gxw = min(ntx, 256 / TX);
+    const int gyh = min(nty, max(1, 32 / gxw));
+    int tx_i, ty_i, zc_i;
+    tile_of_block(blockIdx.x, gridDim.x, ntx, nty, gxw, gyh, tx_i, ty_i, zc_i);
+    const int z0 = zc_i * zchunk;
+    fused_tile<NC, TX, TY, true>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0, min(z0 + zchunk, p.nz), mom);
 }
 
 // Many independent lattices in one launch: each workgroup takes one entry of the work
@@ -628,13 +723,14 @@ __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused(
 template <int NC, int TX, int TY>
 __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused_batch(
     const BatchInstance* __restrict__ inst, const WorkItem* __restrict__ work, int parity) {
-    __shared__ FusedTile<NC, TX, TY> L;
+    __shared__ FusedTile<NC, TX, TY, false> L;
     const int64_t bid = xcd_remap_f(blockIdx.x, gridDim.x);
     const WorkItem w = work[bid];
     const BatchInstance& bi = inst[w.inst];
     const DevParams p = bi.p;
     const int c = bi.cur ^ parity;
-    fused_tile<NC, TX, TY>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0, w.z0, w.z1);
+    fused_tile<NC, TX, TY, false>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0, w.z0, w.z1,
+                                  nullptr);
 }
 
 template <int NC, int TX, int TY>
@@ -645,6 +741,26 @@ static hipError_t launch_fused_t(const DevParams& p, const Buffers& b, int zchun
     hipLaunchKernelGGL((k_fused<NC, TX, TY>), dim3((unsigned)nblk), dim3(NC * TX * TY), 0, s, p, b.h, b.hn, b.D,
                        b.Dn, b.flags, zchunk);
     return hipGetLastError();
+}
+
+template <int NC, int TX, int TY>
+static hipError_t launch_fused2_t(const DevParams& p, const Buffers& b, int zchunk, hipStream_t s) {
+    const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
+    const int nzc = (p.nz + zchunk - 1) / zchunk;
+    const int64_t nblk = (int64_t)ntx * nty * nzc;
+    hipLaunchKernelGGL((k_fused2<NC, TX, TY>), dim3((unsigned)nblk), dim3(NC * TX * TY), 0, s, p, b.h, b.hn, b.D,
+                       b.Dn, b.mom, b.flags, zchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s) {
+    const int zc = t.zchunk > 0 ? t.zchunk : p.nz;
+    if (p.nc == 2) {
+        if (t.tile == 2) return launch_fused2_t<2, 16, 16>(p, b, zc, s);
+        return launch_fused2_t<2, 32, 8>(p, b, zc, s);
+    }
+    if (t.tile == 2) return launch_fused2_t<1, 16, 16>(p, b, zc, s);
+    return launch_fused2_t<1, 32, 8>(p, b, zc, s);
 }
 
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,

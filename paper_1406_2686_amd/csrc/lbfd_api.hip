@@ -172,6 +172,11 @@ hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
             e = launch_moments(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_forces(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_collide(c->dp, c->buf, c->stream);
+        } else if (c->tune.path == LBFD_PATH_TWOPASS) {
+            Tuning tt = c->tune;
+            if (tt.zchunk <= 0) tt.zchunk = auto_zchunk(c->grid, tt.tile);
+            e = launch_moments(c->dp, c->buf, c->stream);
+            if (e == hipSuccess) e = launch_fused2(c->dp, c->buf, tt, c->stream);
         } else {
             Tuning tt = c->tune;
             if (tt.zchunk <= 0) tt.zchunk = auto_zchunk(c->grid, tt.tile);
@@ -524,7 +529,8 @@ lbfd_status lbfd_set_state(lbfd_ctx* c, const void* host, uint64_t bytes) {
 
 lbfd_status lbfd_set_tuning(lbfd_ctx* c, const lbfd_tuning* t) {
     if (!c || !t) return LBFD_EINVAL;
-    if (t->path != LBFD_PATH_FUSED && t->path != LBFD_PATH_SPLIT) return fail(c, LBFD_EINVAL, "bad path");
+    if (t->path != LBFD_PATH_FUSED && t->path != LBFD_PATH_SPLIT && t->path != LBFD_PATH_TWOPASS)
+        return fail(c, LBFD_EINVAL, "bad path");
     if (t->tile < LBFD_TILE_32x8 || t->tile > LBFD_TILE_16x16) return fail(c, LBFD_EINVAL, "bad tile");
     if (t->zchunk < 0) return fail(c, LBFD_EINVAL, "zchunk must be >= 0");
     c->tune = Tuning{t->path, t->tile, t->zchunk};

@@ -79,6 +79,8 @@ hipError_t launch_clear_flags(const Buffers& b, hipStream_t s);
 hipError_t launch_set_flags(const Buffers& b, unsigned v, hipStream_t s);
 // the fused single-pass step (k_fused.hip)
 hipError_t launch_fused(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
+// second pass of the two-pass step (after launch_moments over the same time level)
+hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,
                               int parity, hipStream_t s);
 void fused_tile_shape(int ncomp, int tile, int* tx, int* ty);

@@ -238,8 +238,53 @@ def test_fused_launch_shapes_agree_bitwise_and_match_split_path(lb):
     lat.set_tuning(lb.PATH_SPLIT)
     lat.step(40)
     s = lat.get_fields()
+    lat.close()
     e = report("fused-vs-split", ref, s)
     assert e["u"] < 2e-6 and e["C"] < 1e-7 and e["rho"] < 1e-7
+    # two-pass step (moments pass + one pass over the tile): same arithmetic per node as the
+    # fused pass except the order of the two species' momenta in j, bitwise identical
+    # across its own launch shapes
+    ref2 = None
+    for tile, zc in [("32x8", 0), ("16x16", 3), ("32x8", 23)]:
+        lat = lb.from_workload(wl)
+        lat.set_tuning(lb.PATH_TWOPASS, tile, zc)
+        lat.step(40)
+        f = lat.get_fields()
+        lat.close()
+        if ref2 is None:
+            ref2 = f
+        else:
+            for a, b in zip(f, ref2):
+                assert np.array_equal(a, b), ("two-pass", tile, zc)
+    e = report("fused-vs-two-pass", ref, ref2)
+    assert e["u"] < 2e-6 and e["C"] < 1e-7 and e["rho"] < 1e-7
+
+
+@pytest.mark.parametrize("case", ["cfg1_physics", "couette", "ragged_polyB"])
+def test_two_pass_step_matches_oracle(lb, case):
+    """The two-pass launch shape against the FP64 oracle on the full 128x64x128 droplet,
+    the FENE-P Couette and a ragged droplet grid."""
+    if case == "cfg1_physics":
+        wl, steps = workloads.droplet_cfg1(De=1.0, variant="physics"), 100
+    elif case == "couette":
+        wl, steps = workloads.couette_fenep(), 4000
+    else:
+        wl = workloads.droplet_shear(nx=37, ny=21, nz=29, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                     polymer_phase="B", De=0.5, U=0.008)
+        steps = 1500
+    lat = lb.from_workload(wl)
+    lat.set_tuning(lb.PATH_TWOPASS)
+    lat.step(steps)
+    g = lat.get_fields()
+    dg = lat.diagnostics()
+    lat.close()
+    o = oracle.from_workload(wl)
+    assert o.step(steps) == 0
+    r = o.get_fields()
+    do = o.diagnostics()
+    e = report(f"two-pass-{case}", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert abs(dg["D"] - do["D"]) < 1e-5
 
 
 def test_full_size_droplet_sampled_window(lb):
