@@ -24,6 +24,9 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per node and step (FP32): populations read + written
 # (2 x ncomp x 19 x 4) and C read + written (2 x 6 x 4)
 ALG_BYTES = {1: 200, 2: 352}
+# kernels of one step per launch path (the two-pass step is the default)
+STEP_KERNELS = {0: "k_fused (one launch per step)", 1: "k_moments + k_forces + k_collide",
+                2: "k_moments + k_fused2 (two launches per step; bytes are the step's minimum)"}
 
 
 def log(*a):
@@ -31,10 +34,10 @@ def log(*a):
 
 
 def recorded_traffic(workload):
-    """HBM bytes per launch of the fused kernel on `workload`, from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
-    copy of known size).  Returned only while the kernel sources hash to the profiled ones;
-    a changed kernel gives None until it is profiled again."""
+    """HBM bytes per step (the step's launches together) on `workload`, from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a copy of known size).  Returned only while the kernel sources hash to the
+    profiled ones; a changed kernel gives None until it is profiled again."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"k_fused_{workload.replace('droplet_shear_', 'droplet_')}.md")
@@ -321,6 +324,7 @@ def main():
     torch.cuda.synchronize()
     log(f"init {nx}x{ny}x{nz}: {time.perf_counter() - t_init:.1f} s")
 
+    tuning = lat.get_tuning()
     d0 = lat.diagnostics()
     lat.step_async(args.warmup)
     torch.cuda.synchronize()
@@ -356,7 +360,7 @@ def main():
     alg = ALG_BYTES[2] * N
     achieved = alg / (step_ms * 1e-3) / 1e9
     rec = recorded_traffic(f"droplet_shear_{nx}x{ny}x{nz}")
-    traffic = None if rec is None else round(rec["bytes_per_launch"] / (step_ms * 1e-3) / 1e9, 1)
+    traffic = None if rec is None else round(rec["bytes_per_step"] / (step_ms * 1e-3) / 1e9, 1)
     mass_drift = max(abs(d1["mass_A"] - d0["mass_A"]) / d0["mass_A"],
                      abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"])
     out = {
@@ -365,13 +369,16 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"droplet_shear_{nx}x{ny}x{nz}", "nodes": N, "ncomp": 2,
+                   "launch": {"path": ["fused", "split", "two-pass"][tuning["path"]], "tile": tuning["tile"],
+                              "zchunk": tuning["zchunk"]},
                    "droplet_R": wl0["meta"]["R"], "polymer": "matrix (L2=400, De=1)",
                    "diag_every": args.diag_every, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_fused (the whole step, one launch per step)",
+                     "kernel": STEP_KERNELS.get(tuning["path"], "?"),
+                     "launches_per_step": 2 if tuning["path"] == 2 else (3 if tuning["path"] == 1 else 1),
                      "alg_bytes_per_node": ALG_BYTES[2], "event_ms_per_step": round(step_ms, 4),
-                     "traffic_bytes_per_launch": None if rec is None else rec["bytes_per_launch"],
+                     "traffic_bytes_per_step": None if rec is None else rec["bytes_per_step"],
                      "traffic_source": None if rec is None else rec["path"]},
         "checks": {"fault_flags": flags, "mass_drift_rel": mass_drift, "D_final": d1["D"]},
     }

@@ -160,8 +160,8 @@ lbfd_status lbfd_checkpoint_bytes(lbfd_ctx* ctx, uint64_t* bytes);
 lbfd_status lbfd_get_state(lbfd_ctx* ctx, void* host, uint64_t bytes);
 lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
 
-/* Launch shape of the step.  path: LBFD_PATH_FUSED (one pass over HBM per step, the
- * default), LBFD_PATH_TWOPASS (a streaming moments pass, then one pass that reads the
+/* Launch shape of the step.  path: LBFD_PATH_FUSED (one pass over HBM per step),
+ * LBFD_PATH_TWOPASS (the default: a streaming moments pass, then one pass that reads the
  * moments and C with their halos and only the tile's own populations) or LBFD_PATH_SPLIT
  * (three passes: moments, forces, collide; kept as a cross-check).  The three paths compute
  * the same step; their results agree to FP32 rounding.  tile: LBFD_TILE_32x8 / 32x16 /
@@ -174,6 +174,8 @@ lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
 #define LBFD_TILE_32x8 0
 #define LBFD_TILE_32x16 1
 #define LBFD_TILE_16x16 2
+#define LBFD_TILE_64x8 3   /* two-pass step only (one 64-lane row per wavefront); the fused and
+                              split steps and batches run it as 32x8 */
 typedef struct {
     int32_t path;
     int32_t tile;
@@ -183,8 +185,9 @@ typedef struct {
 lbfd_status lbfd_set_tuning(lbfd_ctx* ctx, const lbfd_tuning* t);
 lbfd_status lbfd_get_tuning(lbfd_ctx* ctx, lbfd_tuning* t);
 
-/* Launch-shape autotuner (single lattice): times the fused step for every tile shape and a
- * range of z-chunks on the current state, `reps` launches each, and keeps the fastest
+/* Launch-shape autotuner (single lattice): times the two-pass and the fused step for every
+ * tile shape and a range of z-chunks on the current state, `reps` launches each, and keeps
+ * the fastest
  * (also returned in *best with its time in *ms_per_step; either may be NULL).  The trial
  * launches recompute the next time level from the current one without advancing, so the
  * lattice state, step counter and fault flags are unchanged.  ESTATE before set_fields. */

@@ -75,7 +75,7 @@ class Tuning(ctypes.Structure):
 
 
 PATH_FUSED, PATH_SPLIT, PATH_TWOPASS = 0, 1, 2
-TILES = {"32x8": 0, "32x16": 1, "16x16": 2}
+TILES = {"32x8": 0, "32x16": 1, "16x16": 2, "64x8": 3}
 
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)

@@ -128,8 +128,8 @@ struct FusedTile {
     float rho[3][NC][A2];       // delta rho per component (ring over planes)
     float cs[3][8][A2];         // D = C - I (6), s, s1 (ring over planes)
     float u[3][3][A1];          // total j (after A2), u (after B) (ring over planes)
-    float Fo[NC][3][NT];        // species forces of the tile nodes, phase B -> C
-    float fpl[2][NT];           // f+(phi) of the tile nodes, planes q and q-1
+    float Fo[NC][3][A1];        // species forces on the tile + 1-node halo, phase B -> C
+    float fpl[2][A1];           // f+(phi) on the tile + 1-node halo, planes q and q-1
     float jc[TP ? 1 : NC][3][TP ? 1 : A1];                  // momentum per component
     float pop[TP ? 1 : 2][TP ? 1 : NC][kQ][TP ? 1 : NT];     // own populations, planes q, q-1
 };
@@ -245,7 +245,7 @@ __device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, T
     }
     L.cs[sq][6][i2] = pm * p.L2m3 * inv;
     L.cs[sq][7][i2] = pm * trd * inv;
-    if (NC == 2 && lx >= 0 && lx < TX && ly >= 0 && ly < TY) L.fpl[s2][ly * TX + lx] = 0.5f * (1.0f + th);
+    if (NC == 2 && lx >= -1 && lx <= TX && ly >= -1 && ly <= TY) L.fpl[s2][(ly + 1) * T::W1 + lx + 1] = 0.5f * (1.0f + th);
     if (!TP && lx >= -1 && lx <= TX && ly >= -1 && ly <= TY) {
         const int i1 = (ly + 1) * T::W1 + lx + 1;
 #pragma unroll
@@ -329,6 +329,91 @@ struct MomLoad {
     float d[6];
 };
 
+// Node quantities the collision needs, read from LDS: velocity, species force, density,
+// relaxation, and (stress coupling, eq. MODEtransformation) the species' share T_s of the
+// polymer stress.
+struct CollideIn {
+    float u[3], F[3];
+    float drs, rs, om, cfac, uF, b, trs3;
+    float Ts[6];
+    bool stress;
+};
+
+template <int NC, int TX, int TY, bool TP>
+__device__ __forceinline__ CollideIn collide_in(const DevParams& p, FusedTile<NC, TX, TY, TP>& L, int sr, int p2,
+                                                int comp, int i1, int i2) {
+    // no FMA contraction in the collision helpers: the same node is collided by its own
+    // lane in one launch shape and by a tile-edge lane of a neighbouring tile in another,
+    // and contraction would depend on which results the caller uses
+#pragma clang fp contract(off)
+    CollideIn c;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c.u[d] = L.u[sr][d][i1];
+        c.F[d] = L.Fo[comp][d][i1];
+    }
+    c.drs = L.rho[sr][comp][i2];
+    c.rs = (comp == 0 ? p.rho0[0] : p.rho0[1]) + c.drs;
+    const float uu = fmaf(c.u[2], c.u[2], fmaf(c.u[1], c.u[1], c.u[0] * c.u[0]));
+    const float tau = NC == 2 ? fmaf(p.tauA - p.tauB, L.fpl[p2][i1], p.tauB) : p.tauA;
+    c.om = 1.0f / tau;
+    c.cfac = fmaf(-0.5f, c.om, 1.0f);
+    c.uF = fmaf(c.u[2], c.F[2], fmaf(c.u[1], c.F[1], c.u[0] * c.F[0]));
+    c.b = -1.5f * uu;
+    c.stress = p.coupling == 1 && p.pstress != 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c.Ts[k] = 0.0f;
+    if (c.stress) {
+        const float rtot = p.rho0[0] + L.rho[sr][0][i2] + (NC == 2 ? p.rho0[1] + L.rho[sr][NC - 1][i2] : 0.0f);
+        const float share = c.rs / rtot;
+        const float sv = share * L.cs[sr][6][i2], s1v = share * L.cs[sr][7][i2];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) c.Ts[k] = k < 3 ? fmaf(sv, L.cs[sr][k][i2], s1v) : sv * L.cs[sr][k][i2];
+    }
+    c.trs3 = (c.Ts[0] + c.Ts[1] + c.Ts[2]) * (1.0f / 3.0f);
+    return c;
+}
+
+// rest population: h - (h - h_eq)/tau + (1 - 1/(2 tau)) S
+__device__ __forceinline__ float collide_rest(const CollideIn& c, float ha) {
+#pragma clang fp contract(off)
+    const float w = wgt(0);
+    const float heq0 = w * fmaf(c.rs, c.b, c.drs) + (c.stress ? (4.5f * w) * c.trs3 : 0.0f);
+    return fmaf(c.cfac, w * (-3.0f * c.uF), fmaf(-c.om, ha - heq0, ha));
+}
+
+// Opposite pair (a, a+1), c_{a+1} = -c_a, given c_a = (ex, ey, ez) and its weight w: the
+// equilibrium and the source split into parts even and odd in c, formed once; each
+// population is relaxed as h - (h - h_eq)/tau + (1 - 1/(2 tau)) S, the form whose rounding
+// keeps the species mass drift smallest.  Fixed fma pattern, contraction off: the result
+// is the same whether c_a is a compile-time constant (own nodes) or a run-time value (the
+// tile-edge lanes that collide a halo node's inbound directions).
+__device__ __forceinline__ void collide_pair_c(const CollideIn& c, float ex, float ey, float ez, float w, float ha,
+                                               float hb, float& pa, float& pb) {
+#pragma clang fp contract(off)
+    const float cu = fmaf(ez, c.u[2], fmaf(ey, c.u[1], ex * c.u[0]));
+    const float cF = fmaf(ez, c.F[2], fmaf(ey, c.F[1], ex * c.F[0]));
+    float ee = w * fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs);  // equilibrium, even part
+    if (c.stress) {
+        const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
+                          2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
+        ee = fmaf(-4.5f * w, cTc - c.trs3, ee);
+    }
+    const float eo = ((3.0f * w) * c.rs) * cu;                 // equilibrium, odd part
+    const float se = w * fmaf(9.0f * cu, cF, -3.0f * c.uF);    // source, even part
+    const float so = (3.0f * w) * cF;                          // source, odd part
+    pa = fmaf(c.cfac, se + so, fmaf(-c.om, ha - (ee + eo), ha));
+    pb = fmaf(c.cfac, se - so, fmaf(-c.om, hb - (ee - eo), hb));
+}
+
+__device__ __forceinline__ void collide_pair(const CollideIn& c, int a, float ha, float hb, float& pa, float& pb) {
+    collide_pair_c(c, float(cx(a)), float(cy(a)), float(cz(a)), wgt(a), ha, hb, pa, pb);
+}
+
+// the pairs with c_x != 0 (their odd member has c_x = +1): 1, 7, 9, 11, 13
+__host__ __device__ constexpr int xpair(int m) { return m == 0 ? 1 : 5 + 2 * m; }
+__host__ __device__ constexpr int xpair_index(int a) { return a == 1 ? 0 : (a - 5) / 2; }
+
 // One workgroup's share of a step: tile [x0, x0+TX) x [y0, y0+TY), planes [z0, z1).
 // TP = false: single pass, the moments are formed here from the populations of the tile
 // and its halo.  TP = true: second pass of the two-pass step, delta rho and j of every
@@ -391,7 +476,6 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     constexpr int KP = (T::A2 + T::NTH - 1) / T::NTH;
     MomLoad<NC> mpf[KP];
     uint32_t mpos[KP];
-    float own_pop[kQ];
     if (TP) {
 #pragma unroll
         for (int i = 0; i < KP; ++i) {
@@ -400,8 +484,6 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
             const int gy = min(max(y0 + ly, 0), ny - 1);
             mpos[i] = (uint32_t)gy * (uint32_t)nx + (uint32_t)wrapn(x0 + lx, nx);
         }
-#pragma unroll
-        for (int a = 0; a < kQ; ++a) own_pop[a] = 0.0f;
     }
     auto issue_mom = [&](int zq) {
         const uint32_t zoff = (uint32_t)wrapn(zq, nz) * plane;
@@ -481,109 +563,105 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 if (gy < 0 || gy >= ny) continue;  // ghost velocities come from the wall rule
                 float Fs[2][3];
                 phase_b<NC, TX, TY, TP>(p, L, sp, sr, sq, lx, ly, Fs);
-                if (k < T::NT) {
+                const int i1 = (ly + 1) * T::W1 + lx + 1;
 #pragma unroll
-                    for (int s = 0; s < NC; ++s)
+                for (int s = 0; s < NC; ++s)
 #pragma unroll
-                        for (int d = 0; d < 3; ++d) L.Fo[s][d][k] = Fs[s][d];
-                }
+                    for (int d = 0; d < 3; ++d) L.Fo[s][d][i1] = Fs[s][d];
             }
         }
         lds_barrier();
 
         // ---------------- C: collide + stream plane q-1 (own node, own component) ----------
-        // BGK with the forcing source (eq. LB, Lambda = I/tau(phi)).  For an opposite pair
-        // (a, a+1) the equilibrium and the source split into parts even and odd in c, formed
-        // once per pair; each population is then relaxed as h - (h - h_eq)/tau + (1 -
-        // 1/(2 tau)) S, the form whose rounding keeps the species mass drift smallest.
-        if (do_c) {
+        // BGK with the forcing source (eq. LB, Lambda = I/tau(phi)), per opposite pair.
+        // Streaming stores are x-aligned: a lane stores, at its own x, the value arriving
+        // from x - c_x, taken from the neighbouring lane of its row; the edge lane of a row
+        // collides the halo node's inbound directions itself (same arithmetic, same inputs),
+        // so every row of every direction is written as whole lines by one workgroup.
+        if (q >= z0 + 1 && q <= z1 && ogy < ny) {
             const int sr = ((q - 1) % 3 + 3) % 3;
             const int p2 = s2 ^ 1;
             const int r = wrapn(q - 1, nz);
-            float u[3], F[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                u[d] = L.u[sr][d][oi1];
-                F[d] = L.Fo[comp][d][nid];
-            }
-            const float drs = L.rho[sr][comp][oi2];
-            const float rs = (comp == 0 ? p.rho0[0] : p.rho0[1]) + drs;
-            const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-            const float tau = NC == 2 ? p.tauB + (p.tauA - p.tauB) * L.fpl[p2][nid] : p.tauA;
-            const float om = 1.0f / tau;
-            const float cfac = 1.0f - 0.5f * om;
-            const float uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-            const float b = -1.5f * uu;
-            // stress coupling (eq. MODEtransformation): T_s = (rho_s/rho) T lowers the second
-            // moment of this species' equilibrium by -4.5 w (c.T_s.c - tr T_s/3) per direction
-            const bool stress_eq = p.coupling == 1 && p.pstress != 0.0f;
-            float Ts[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (stress_eq) {
-                const float rtot = p.rho0[0] + L.rho[sr][0][oi2] + (NC == 2 ? p.rho0[1] + L.rho[sr][NC - 1][oi2] : 0.0f);
-                const float share = rs / rtot;
-                const float sv = share * L.cs[sr][6][oi2], s1v = share * L.cs[sr][7][oi2];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) Ts[k] = sv * L.cs[sr][k][oi2] + (k < 3 ? s1v : 0.0f);
-            }
-            const float trs3 = (Ts[0] + Ts[1] + Ts[2]) * (1.0f / 3.0f);
+            const int txe = min(TX, nx - x0);  // columns of this tile inside the lattice
+            const bool left_edge = olx == 0;
+            const bool right_edge = olx == txe - 1;
             const uint32_t zrow[3] = {(uint32_t)(r == 0 ? nz - 1 : r - 1) * plane, (uint32_t)r * plane,
                                       (uint32_t)(r + 1 == nz ? 0 : r + 1) * plane};
             const uint32_t bself = (zrow[1] + yrow + xcol[1]) * 4u;
+            float hpop[kQ];
+            if constexpr (TP) {
+#pragma unroll
+                for (int a = 0; a < kQ; ++a) hpop[a] = ld_off(hs + (size_t)a * N, bself);
+            } else {
+#pragma unroll
+                for (int a = 0; a < kQ; ++a) hpop[a] = L.pop[TP ? 0 : p2][TP ? 0 : comp][a][TP ? 0 : nid];
+            }
+            // the halo nodes' post-collision values that stream into this row's edge nodes:
+            // lane m < 5 of the row collides direction xpair(m) (c_x = +1) of the left halo
+            // node, lane 5 + m direction xpair(m) + 1 (c_x = -1) of the right one
+            float hval = 0.0f;
+            if (olx < 10) {
+                const bool lside = olx < 5;
+                const int m = lside ? olx : olx - 5;
+                const int ap = m == 0 ? 1 : 5 + 2 * m;  // xpair(m)
+                const float ex = 1.0f;
+                const float ey = ap == 7 ? 1.0f : (ap == 9 ? -1.0f : 0.0f);
+                const float ez = ap == 11 ? 1.0f : (ap == 13 ? -1.0f : 0.0f);
+                const float w = ap == 1 ? wgt(1) : wgt(7);
+                const int dl = lside ? -1 - olx : txe - olx;  // halo column relative to this lane
+                const uint32_t hx = (uint32_t)wrapn(lside ? x0 - 1 : x0 + txe, nx);  // halo column
+                const uint32_t bo = (zrow[1] + yrow + hx) * 4u;
+                const float hv = ld_off(hs + (size_t)(lside ? ap : ap + 1) * N, bo);
+                const CollideIn in = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, oi1 + dl, oi2 + dl);
+                float pa, pb;
+                collide_pair_c(in, ex, ey, ez, w, hv, hv, pa, pb);
+                hval = lside ? pa : pb;
+            }
+            float lin[5], rin[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                lin[m] = __shfl(hval, m, TX);
+                rin[m] = __shfl(hval, 5 + m, TX);
+            }
+            const CollideIn own = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, oi1, oi2);
+            const bool stx = ogx < nx;  // lanes past a ragged edge compute but do not store
             float check;
             {
-                const float w = wgt(0);
-                const float ha = TP ? own_pop[0] : L.pop[TP ? 0 : p2][TP ? 0 : comp][0][TP ? 0 : nid];
-                const float heq0 = w * (drs + rs * b) + (stress_eq ? 4.5f * w * trs3 : 0.0f);
-                const float post = ha - om * (ha - heq0) + cfac * (w * (-3.0f * uF));
-                st_off(hns, bself, post);
+                const float post = collide_rest(own, hpop[0]);
+                if (stx) st_off(hns, bself, post);
                 check = post;
             }
 #pragma unroll
             for (int a = 1; a < kQ; a += 2) {
-                const float w = wgt(a);
-                const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
-                const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
-                float ee = w * (drs + rs * (4.5f * cu * cu + b));  // equilibrium, even part
-                if (stress_eq) {
-                    const float cTc = float(cx(a) * cx(a)) * Ts[0] + float(cy(a) * cy(a)) * Ts[1] +
-                                      float(cz(a) * cz(a)) * Ts[2] +
-                                      2.0f * (float(cx(a) * cy(a)) * Ts[3] + float(cx(a) * cz(a)) * Ts[4] +
-                                              float(cy(a) * cz(a)) * Ts[5]);
-                    ee -= 4.5f * w * (cTc - trs3);
-                }
-                const float eo = (3.0f * w) * rs * cu;                   // equilibrium, odd part
-                const float se = w * (9.0f * cu * cF - 3.0f * uF);       // source, even part
-                const float so = (3.0f * w) * cF;                        // source, odd part
+                float pp, pm;
+                collide_pair(own, a, hpop[a], hpop[a + 1], pp, pm);
+                check += pp + pm;
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int bq = a + e;
-                    const float ha = TP ? own_pop[bq] : L.pop[TP ? 0 : p2][TP ? 0 : comp][bq][TP ? 0 : nid];
-                    const float heq = e == 0 ? ee + eo : ee - eo;
-                    const float src = e == 0 ? se + so : se - so;
-                    const float post = ha - om * (ha - heq) + cfac * src;
-                    check += post;
+                    const float post = e == 0 ? pp : pm;
+                    float v = post;
+                    if (cx(bq) > 0) {
+                        v = __shfl_up(post, 1, TX);
+                        if (left_edge) v = lin[xpair_index(a)];
+                    } else if (cx(bq) < 0) {
+                        v = __shfl_down(post, 1, TX);
+                        if (right_edge) v = rin[xpair_index(a)];
+                    }
                     const int yd = ogy + cy(bq);
                     if (yd >= 0 && yd < ny) {
-                        const uint32_t dst = zrow[cz(bq) + 1] + yrow + (uint32_t)(cy(bq) * nx) + xcol[cx(bq) + 1];
-                        st_off(hns + (size_t)bq * N, dst * 4u, post);
-                    } else {
+                        const uint32_t dst = zrow[cz(bq) + 1] + yrow + (uint32_t)(cy(bq) * nx) + xcol[1];
+                        if (stx) st_off(hns + (size_t)bq * N, dst * 4u, v);
+                    } else if (stx) {
                         // moving-wall bounce-back (Sec. 3.1 walls): the link returns as opp(bq)
                         const float* uw = yd < 0 ? p.ub : p.ut;
                         const float cuw = cx(bq) * uw[0] + cz(bq) * uw[2];
-                        st_off(hns + (size_t)opp(bq) * N, bself, post - 6.0f * wgt(bq) * rs * cuw);
+                        st_off(hns + (size_t)opp(bq) * N, bself, post - 6.0f * wgt(bq) * own.rs * cuw);
                     }
                 }
             }
-            if (!isfinite(check)) bad |= 1u;
+            if (stx && !isfinite(check)) bad |= 1u;
         }
-        if (TP && q >= z0 && q < z1) {
-            // own populations of plane q, collided in the next iteration; the registers were
-            // emptied by phase C just above
-            const uint32_t bo = ((uint32_t)wrapn(q, nz) * plane + own_xy) * 4u;
-#pragma unroll
-            for (int a = 0; a < kQ; ++a) own_pop[a] = ld_off(hs + (size_t)a * N, bo);
-        }
-
         // ---------------- D: FENE-P on plane q-2 (own node, component-0 threads) ----------
         if (fene && q >= z0 + 2 && active) {
             const int t = wrapn(q - 2, nz);
@@ -703,7 +781,7 @@ __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused(
 // population ring its LDS (72 KB for 32x8, two components) admits two workgroups per CU;
 // the launch bound asks for 4 waves per SIMD (128 VGPRs) so that both fit.
 template <int NC, int TX, int TY>
-__global__ __launch_bounds__(NC* TX* TY, 4) void k_fused2(
+__global__ __launch_bounds__(NC* TX* TY, NC == 2 ? 4 : 2) void k_fused2(
     DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
     float* __restrict__ Dn, const float* __restrict__ mom, unsigned* __restrict__ flags, int zchunk) {
     __shared__ FusedTile<NC, TX, TY, true> L;
@@ -757,9 +835,11 @@ hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, 
     const int zc = t.zchunk > 0 ? t.zchunk : p.nz;
     if (p.nc == 2) {
         if (t.tile == 2) return launch_fused2_t<2, 16, 16>(p, b, zc, s);
+        if (t.tile == 3) return launch_fused2_t<2, 64, 8>(p, b, zc, s);
         return launch_fused2_t<2, 32, 8>(p, b, zc, s);
     }
     if (t.tile == 2) return launch_fused2_t<1, 16, 16>(p, b, zc, s);
+    if (t.tile == 3) return launch_fused2_t<1, 64, 8>(p, b, zc, s);
     return launch_fused2_t<1, 32, 8>(p, b, zc, s);
 }
 

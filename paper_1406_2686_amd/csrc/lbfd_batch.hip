@@ -242,7 +242,7 @@ lbfd_status lbfd_batch_set_fields(lbfd_batch* b, int32_t i, const double* rho, c
 lbfd_status lbfd_batch_set_tuning(lbfd_batch* b, const lbfd_tuning* t) {
     if (!b || !t) return LBFD_EINVAL;
     if (t->path != LBFD_PATH_FUSED) return bfail(b, LBFD_EINVAL, "the batch runs the fused path only");
-    if (t->tile < LBFD_TILE_32x8 || t->tile > LBFD_TILE_16x16 || t->zchunk < 0) return bfail(b, LBFD_EINVAL, "bad tuning");
+    if (t->tile < LBFD_TILE_32x8 || t->tile > LBFD_TILE_64x8 || t->zchunk < 0) return bfail(b, LBFD_EINVAL, "bad tuning");
     b->tune = Tuning{t->path, t->tile, t->zchunk};
     b->tables_dirty = true;
     return LBFD_OK;
@@ -423,18 +423,28 @@ lbfd_status lbfd_autotune(lbfd_ctx* c, int32_t reps, lbfd_tuning* best, double* 
     c->flags_seen |= saved;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBFD_EDEVICE;
-    const std::vector<int> tiles = {LBFD_TILE_32x8, LBFD_TILE_16x16};
     const int zcs[6] = {8, 16, 32, 64, 128, 256};
     Tuning win = c->tune;
     float best_ms = 1e30f;
-    for (int ti : tiles) {
+    // a trial step writes the other buffer (and the moments scratch) but does not swap,
+    // so the state is unchanged
+    auto trial = [&](const Tuning& t) -> hipError_t {
+        if (t.path == LBFD_PATH_TWOPASS) {
+            hipError_t e = launch_moments(c->dp, c->buf, c->stream);
+            return e != hipSuccess ? e : launch_fused2(c->dp, c->buf, t, c->stream);
+        }
+        return launch_fused(c->dp, c->buf, t, c->stream);
+    };
+    for (int path : {LBFD_PATH_TWOPASS, LBFD_PATH_FUSED})
+    for (int ti : {LBFD_TILE_32x8, LBFD_TILE_16x16, LBFD_TILE_64x8}) {
+        if (ti == LBFD_TILE_64x8 && path != LBFD_PATH_TWOPASS) continue;
         for (int zc : zcs) {
             if (zc > c->grid.nz && zc != 8) continue;
-            Tuning t{LBFD_PATH_FUSED, ti, std::min(zc, c->grid.nz)};
-            if (launch_fused(c->dp, c->buf, t, c->stream) != hipSuccess) return LBFD_EDEVICE;
+            Tuning t{path, ti, std::min(zc, c->grid.nz)};
+            if (trial(t) != hipSuccess) return LBFD_EDEVICE;
             (void)hipEventRecord(e0, c->stream);
             for (int r = 0; r < reps; ++r)
-                if (launch_fused(c->dp, c->buf, t, c->stream) != hipSuccess) return LBFD_EDEVICE;
+                if (trial(t) != hipSuccess) return LBFD_EDEVICE;
             (void)hipEventRecord(e1, c->stream);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;

@@ -245,7 +245,7 @@ def test_fused_launch_shapes_agree_bitwise_and_match_split_path(lb):
     # fused pass except the order of the two species' momenta in j, bitwise identical
     # across its own launch shapes
     ref2 = None
-    for tile, zc in [("32x8", 0), ("16x16", 3), ("32x8", 23)]:
+    for tile, zc in [("32x8", 0), ("16x16", 3), ("64x8", 5), ("64x8", 0), ("32x8", 23)]:
         lat = lb.from_workload(wl)
         lat.set_tuning(lb.PATH_TWOPASS, tile, zc)
         lat.step(40)
