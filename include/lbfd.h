@@ -154,28 +154,35 @@ lbfd_status lbfd_get_fields_box(lbfd_ctx* ctx, int32_t x0, int32_t y0, int32_t z
 /* FP64 diagnostics record of the current state.  Synchronises the stream. */
 lbfd_status lbfd_diagnostics(lbfd_ctx* ctx, lbfd_diag* out);
 
-/* Raw checkpoint of the device state (FP32 populations and C - I, step counter, flags):
- * lbfd_checkpoint_bytes gives the size; get copies device -> host, set host -> device. */
+/* Raw checkpoint of the device state (FP32 populations, C - I and the moments delta rho, j
+ * of the current level, step counter, flags): lbfd_checkpoint_bytes gives the size; get
+ * copies device -> host, set host -> device.  A run restarted from a checkpoint continues
+ * bitwise like the run that wrote it, on every path. */
 lbfd_status lbfd_checkpoint_bytes(lbfd_ctx* ctx, uint64_t* bytes);
 lbfd_status lbfd_get_state(lbfd_ctx* ctx, void* host, uint64_t bytes);
 lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
 
 /* Launch shape of the step.  path: LBFD_PATH_FUSED (one pass over HBM per step),
  * LBFD_PATH_TWOPASS (the default: a streaming moments pass, then one pass that reads the
- * moments and C with their halos and only the tile's own populations) or LBFD_PATH_SPLIT
- * (three passes: moments, forces, collide; kept as a cross-check).  The three paths compute
- * the same step; their results agree to FP32 rounding.  tile: LBFD_TILE_32x8 / 32x16 /
- * 16x16 (x by y nodes per workgroup of the fused and two-pass steps; 32x16 runs as 32x8).
- * zchunk: planes per workgroup along z, 0 = automatic.  Within one path, results are
- * identical for every tile and zchunk; only speed changes. */
+ * moments and C with their halos and only the tile's own populations), LBFD_PATH_CHAINED
+ * (the two-pass step whose second pass also forms the moments of the next level, so that a
+ * run of steps needs one launch per step and the moments pass runs only when the moments
+ * of the current level are not at hand: after set_fields, another path or a batch; 64x8
+ * tiles whatever `tile` says) or LBFD_PATH_SPLIT (three passes: moments, forces, collide;
+ * kept as a cross-check).  The paths compute the same step; their results agree to FP32
+ * rounding.  tile: LBFD_TILE_32x8 / 32x16 / 16x16 (x by y nodes per workgroup of the fused
+ * and two-pass steps; 32x16 runs as 32x8).  zchunk: planes per workgroup along z, 0 =
+ * automatic.  Within one path, results are identical for every tile and zchunk; only speed
+ * changes. */
 #define LBFD_PATH_FUSED 0
 #define LBFD_PATH_SPLIT 1
 #define LBFD_PATH_TWOPASS 2
+#define LBFD_PATH_CHAINED 3
 #define LBFD_TILE_32x8 0
 #define LBFD_TILE_32x16 1
 #define LBFD_TILE_16x16 2
-#define LBFD_TILE_64x8 3   /* two-pass step only (one 64-lane row per wavefront); the fused and
-                              split steps and batches run it as 32x8 */
+#define LBFD_TILE_64x8 3   /* two-pass and chained steps only (one 64-lane row per wavefront);
+                              the fused and split steps and batches run it as 32x8 */
 typedef struct {
     int32_t path;
     int32_t tile;
@@ -185,9 +192,9 @@ typedef struct {
 lbfd_status lbfd_set_tuning(lbfd_ctx* ctx, const lbfd_tuning* t);
 lbfd_status lbfd_get_tuning(lbfd_ctx* ctx, lbfd_tuning* t);
 
-/* Launch-shape autotuner (single lattice): times the two-pass and the fused step for every
- * tile shape and a range of z-chunks on the current state, `reps` launches each, and keeps
- * the fastest
+/* Launch-shape autotuner (single lattice): times the chained, two-pass and fused steps for
+ * every tile shape they take and a range of z-chunks on the current state, `reps` launches
+ * each, and keeps the fastest
  * (also returned in *best with its time in *ms_per_step; either may be NULL).  The trial
  * launches recompute the next time level from the current one without advancing, so the
  * lattice state, step counter and fault flags are unchanged.  ESTATE before set_fields. */

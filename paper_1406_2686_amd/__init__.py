@@ -74,7 +74,7 @@ class Tuning(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
-PATH_FUSED, PATH_SPLIT, PATH_TWOPASS = 0, 1, 2
+PATH_FUSED, PATH_SPLIT, PATH_TWOPASS, PATH_CHAINED = 0, 1, 2, 3
 TILES = {"32x8": 0, "32x16": 1, "16x16": 2, "64x8": 3}
 
 _P = ctypes.c_void_p

@@ -35,6 +35,17 @@ __host__ __device__ constexpr int sidx(int i, int j) {
     return i == j ? i : ((i + j) == 1 ? 3 : ((i + j) == 2 ? 4 : 5));
 }
 
+// c_a . u_w for a wall velocity with no wall-normal component, the zero terms left out
+// (0 * x is not folded under IEEE rules, and such products of a per-lane wall velocity
+// would otherwise be formed for every direction)
+__host__ __device__ __forceinline__ float wall_cu(int a, const float* uw) {
+    const int ex = cx(a), ez = cz(a);
+    if (ex != 0 && ez != 0) return float(ex) * uw[0] + float(ez) * uw[2];
+    if (ex != 0) return ex > 0 ? uw[0] : -uw[0];
+    if (ez != 0) return ez > 0 ? uw[2] : -uw[2];
+    return 0.0f;
+}
+
 // Periodic wrap for |d| <= 1 offsets.
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 // Wall-normal clamp (ghost layer copies the wall-adjacent node).

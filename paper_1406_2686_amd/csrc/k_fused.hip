@@ -117,7 +117,10 @@ __device__ __forceinline__ void halo1_pos(int k, int& lx, int& ly) {
 
 // LDS of one workgroup.  TP (two-pass step): the moments come from a preceding pass, so
 // the per-component momenta and the ring of own populations are not needed (size 1).
-template <int NC, int TX, int TY, bool TP>
+// MO (chained two-pass step): the tile also forms the moments of the next time level; the
+// partial moments that cross from one row of the tile to the next pass through X, which
+// shares its storage with the species forces (they are dead between phase C and phase B).
+template <int NC, int TX, int TY, bool TP, bool MO = false>
 struct FusedTile {
     static constexpr int NT = TX * TY;    // nodes per tile
     static constexpr int NTH = NC * NT;   // threads: one per (node, component)
@@ -125,10 +128,17 @@ struct FusedTile {
     static constexpr int W1 = TX + 2, H1 = TY + 2, A1 = W1 * H1;
     static constexpr int NH2 = A2 - NT;  // R2 halo nodes
     static constexpr int NH1 = A1 - NT;  // R1 halo nodes
+    static constexpr int NFO = NC * 3 * A1;                     // species forces
+    static constexpr int NXR = NC * 8 * NT;                     // row exchange: 8 values per (node, comp)
+    static constexpr int NXJ = NFO + 3 * NT;                    // forces + the momentum of one component
+    static constexpr int NX = !MO ? 1 : (NXR > NXJ ? NXR : NXJ);
     float rho[3][NC][A2];       // delta rho per component (ring over planes)
     float cs[3][8][A2];         // D = C - I (6), s, s1 (ring over planes)
     float u[3][3][A1];          // total j (after A2), u (after B) (ring over planes)
-    float Fo[NC][3][A1];        // species forces on the tile + 1-node halo, phase B -> C
+    union {
+        float Fo[NC][3][A1];    // species forces on the tile + 1-node halo, phase B -> C
+        float X[NX];            // MO: row exchange after phase C; momentum of one component in A2 -> B
+    };
     float fpl[2][A1];           // f+(phi) on the tile + 1-node halo, planes q and q-1
     float jc[TP ? 1 : NC][3][TP ? 1 : A1];                  // momentum per component
     float pop[TP ? 1 : 2][TP ? 1 : NC][kQ][TP ? 1 : NT];     // own populations, planes q, q-1
@@ -202,8 +212,8 @@ __device__ __forceinline__ void phase_a1(FusedTile<NC, TX, TY, false>& L, int sq
 // two wall-adjacent layers, Sec. 2 boundary condition of C), f+(phi), the stress
 // coefficients s = (eta_p/tau_p) m(phi) f(r), s1 = (eta_p/tau_p) m(phi) (f(r) - 1), and the
 // total momentum.
-template <int NC, int TX, int TY, bool TP>
-__device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, TY, TP>& L, int sq, int s2, int y0, int k,
+template <int NC, int TX, int TY, bool TP, class TL>
+__device__ __forceinline__ void phase_a2(const DevParams& p, TL& L, int sq, int s2, int y0, int k,
                                          unsigned& bad) {
     using T = FusedTile<NC, TX, TY, TP>;
     const int lx = k % T::W2 - 2, ly = k / T::W2 - 2;
@@ -255,8 +265,8 @@ __device__ __forceinline__ void phase_a2(const DevParams& p, FusedTile<NC, TX, T
 
 // Phase B for one in-domain node of plane q-1 at local (lx, ly): Shan-Chen force, polymer
 // stress divergence, species forces and velocity; u replaces j in LDS slot sr.
-template <int NC, int TX, int TY, bool TP>
-__device__ __forceinline__ void phase_b(const DevParams& p, FusedTile<NC, TX, TY, TP>& L, int sp, int sr,
+template <int NC, int TX, int TY, bool TP, class TL>
+__device__ __forceinline__ void phase_b(const DevParams& p, TL& L, int sp, int sr,
                                         int sn, int lx, int ly, float (&Fs)[2][3]) {
     using T = FusedTile<NC, TX, TY, TP>;
     const int i2 = (ly + 2) * T::W2 + lx + 2;
@@ -339,8 +349,8 @@ struct CollideIn {
     bool stress;
 };
 
-template <int NC, int TX, int TY, bool TP>
-__device__ __forceinline__ CollideIn collide_in(const DevParams& p, FusedTile<NC, TX, TY, TP>& L, int sr, int p2,
+template <int NC, int TX, int TY, bool TP, class TL>
+__device__ __forceinline__ CollideIn collide_in(const DevParams& p, TL& L, int sr, int p2,
                                                 int comp, int i1, int i2) {
     // no FMA contraction in the collision helpers: the same node is collided by its own
     // lane in one launch shape and by a tile-edge lane of a neighbouring tile in another,
@@ -414,18 +424,60 @@ __device__ __forceinline__ void collide_pair(const CollideIn& c, int a, float ha
 __host__ __device__ constexpr int xpair(int m) { return m == 0 ? 1 : 5 + 2 * m; }
 __host__ __device__ constexpr int xpair_index(int a) { return a == 1 ? 0 : (a - 5) / 2; }
 
+// Moment contributions of one value v that arrives at a node as population a: delta rho
+// gains v, j gains c_a v (acc = delta rho, j_x, j_y, j_z; c_a is a compile-time constant).
+__device__ __forceinline__ void add_moments(float (&acc)[4], int a, float v) {
+    acc[0] += v;
+    if (cx(a) > 0) acc[1] += v;
+    if (cx(a) < 0) acc[1] -= v;
+    if (cy(a) > 0) acc[2] += v;
+    if (cy(a) < 0) acc[2] -= v;
+    if (cz(a) > 0) acc[3] += v;
+    if (cz(a) < 0) acc[3] -= v;
+}
+
+// The five populations a row sends into the row above it (directions 3, 7, 10, 15, 17,
+// c_y = +1), folded to what the moments of the receiving nodes need: the sum and the
+// x-momentum of the three in-plane ones, then the one going to plane +1 and to plane -1.
+__device__ __forceinline__ void fold_up(float v3, float v7, float v10, float v15, float v17, float (&o)[4]) {
+    o[0] = (v3 + v7) + v10;
+    o[1] = v7 - v10;
+    o[2] = v15;
+    o[3] = v17;
+}
+// ... and into the row below it (directions 4, 8, 9, 18, 16, c_y = -1).
+__device__ __forceinline__ void fold_dn(float v4, float v8, float v9, float v16, float v18, float (&o)[4]) {
+    o[0] = (v4 + v8) + v9;
+    o[1] = v9 - v8;
+    o[2] = v18;
+    o[3] = v16;
+}
+
 // One workgroup's share of a step: tile [x0, x0+TX) x [y0, y0+TY), planes [z0, z1).
 // TP = false: single pass, the moments are formed here from the populations of the tile
 // and its halo.  TP = true: second pass of the two-pass step, delta rho and j of every
 // node come from `mom` (written by the moments pass over the same time level), so only the
 // tile's own populations are read, once, for the collision.
-template <int NC, int TX, int TY, bool TP>
+// MO (with TP, 64-wide tiles): the tile also forms delta rho and j of the next time level
+// for its own nodes and writes them to `mom_out`, so the next step needs no moments pass.
+// A node's new populations come from itself and its 18 neighbours, so the tile also
+// collides, without storing anything,
+//   * the planes z0-1 and z1 next to its chunk (only what crosses into the chunk is kept),
+//   * the rows y0-1 and y0+TY next to it (the five directions entering the tile), and
+//   * the corner nodes of those rows (the diagonal entering the tile's corner),
+// with the same fixed-fma collision as own nodes.  Every moment is therefore the same sum
+// of the same values, added in the same order, whatever the tile position and z-chunk.
+// What a thread receives in its own row goes into a ring of three partial moments in
+// registers (planes p-1, p, p+1 of the source plane p); what goes to the rows above and
+// below is folded to four values per row and passed on through LDS.
+template <int NC, int TX, int TY, bool TP, bool MO>
 __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __restrict__ h,
                                            float* __restrict__ hn, const float* __restrict__ D,
                                            float* __restrict__ Dn, unsigned* __restrict__ flags,
-                                           FusedTile<NC, TX, TY, TP>& L, int x0, int y0, int z0, int z1,
-                                           const float* __restrict__ mom) {
-    using T = FusedTile<NC, TX, TY, TP>;
+                                           FusedTile<NC, TX, TY, TP, MO>& L, int x0, int y0, int z0, int z1,
+                                           const float* __restrict__ mom, float* __restrict__ mom_out) {
+    using T = FusedTile<NC, TX, TY, TP, MO>;
+    static_assert(!MO || (TP && TX == 64), "next-level moments: two-pass body, one tile row per wavefront");
     static_assert(T::NH2 <= T::NT, "one R2 halo node per thread at most");
     static_assert(T::A1 <= 2 * T::NTH, "phase B covers the R1 region in two passes at most");
     static_assert(T::NT % 64 == 0, "a wavefront never straddles two components");
@@ -468,6 +520,21 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     float u_old[3] = {0.f, 0.f, 0.f};
     unsigned bad = 0u;
 
+    // MO: partial next-level moments of the own node (delta rho, j) on planes p-1, p, p+1
+    // (mm, m0, mp) for the plane p collided last; the momentum of a completed plane td waits in jd for
+    // the other component's share
+    float mm[4] = {0.f, 0.f, 0.f, 0.f}, m0[4] = {0.f, 0.f, 0.f, 0.f}, mp[4] = {0.f, 0.f, 0.f, 0.f};
+    float jd[3] = {0.f, 0.f, 0.f};
+    int td = -1;
+    // MO: the wavefront that collides a neighbouring row (-1: the row below the tile, TY:
+    // the row above, 0: none); one per component and side, on four different SIMDs
+    int hrow = 0;
+    if (MO) {
+        const int wv = tid >> 6;
+        if ((wv == 0 || wv == 10) && y0 >= 1) hrow = -1;
+        if ((wv == 1 || wv == 11) && y0 + TY < ny) hrow = TY;
+    }
+
     // plane q+1 is loaded while plane q is processed; the loads land in the registers that
     // phase A1 has just emptied, so no copy (and no early wait) sits on the loop edge
     NodeLoad pf_own, pf_halo;
@@ -509,15 +576,29 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     }
 
     for (int q = z0 - 2; q <= z1 + 1; ++q) {
+        // The lane-dependent indices are derived again in every plane from a copy of the
+        // thread index that the compiler cannot see through (an empty asm statement).
+        // Otherwise it keeps every LDS and global address it can form from them live
+        // across the loop.  With 1024 threads per workgroup a thread has 128 VGPRs, and
+        // those addresses would be spilled to scratch, whose reloads cost HBM traffic.
+        int tq = tid;
+        asm volatile("" : "+v"(tq));
+        const int nid = tq % T::NT;
+        const int olx = nid % TX, oly = nid / TX;
+        const int ogx = x0 + olx, ogy = y0 + oly;
+        const bool active = ogx < nx && ogy < ny;
+        const int oi2 = (oly + 2) * T::W2 + olx + 2;
+        const int oi1 = (oly + 1) * T::W1 + olx + 1;
+        const uint32_t yrow = (uint32_t)min(ogy, ny - 1) * (uint32_t)nx;
+        const uint32_t own_xy = yrow + xcol[1];
         const int sq = ((q % 3) + 3) % 3;
         const int s2 = q & 1;
-        const bool do_c = q >= z0 + 1 && q <= z1 && active;
 
         // ---------------- A1: consume plane q, then request plane q+1 ----------------
         if constexpr (TP) {
 #pragma unroll
             for (int i = 0; i < KP; ++i) {
-                const int k = tid + i * T::NTH;
+                const int k = tq + i * T::NTH;
                 if (k < T::A2) {
                     const int lx = k % T::W2 - 2, ly = k / T::W2 - 2;
 #pragma unroll
@@ -544,14 +625,25 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
         lds_barrier();
 
         // ---------------- A2: ghosts, f+, stress coefficients, total momentum ----------------
-        for (int k = tid; k < T::A2; k += T::NTH) phase_a2<NC, TX, TY, TP>(p, L, sq, s2, y0, k, bad);
+        for (int k = tq; k < T::A2; k += T::NTH) phase_a2<NC, TX, TY, TP>(p, L, sq, s2, y0, k, bad);
+        if constexpr (MO) {
+            // momentum of the plane completed last, second component's share (the exchange
+            // reads of that plane ended at the barrier above)
+            if (NC == 2 && comp == NC - 1 && td >= 0) {
+                if (active) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) L.X[T::NFO + d * T::NT + nid] = jd[d];
+                }
+                td = -1;
+            }
+        }
         lds_barrier();
 
         // ---------------- B: forces and velocity on plane q-1 (tile + 1 halo) -------------
         if (q >= z0) {
             const int sr = ((q - 1) % 3 + 3) % 3;
             const int sp = ((q - 2) % 3 + 3) % 3;
-            for (int k = tid; k < T::A1; k += T::NTH) {
+            for (int k = tq; k < T::A1; k += T::NTH) {
                 int lx, ly;
                 if (k < T::NT) {
                     lx = k % TX;
@@ -570,7 +662,110 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                     for (int d = 0; d < 3; ++d) L.Fo[s][d][i1] = Fs[s][d];
             }
         }
+        if constexpr (MO) {
+            // momentum of the plane completed last: both components' shares, written out
+            // (the forces written above lie below offset NFO)
+            if (comp == 0 && td >= 0) {
+                if (active) {
+                    const uint32_t bt = ((uint32_t)td * plane + own_xy) * 4u;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        float jv = jd[d];
+                        if (NC == 2) jv += L.X[T::NFO + d * T::NT + nid];
+                        st_off(mom_out + (size_t)(NC + d) * N, bt, jv);
+                    }
+                }
+                td = -1;
+            }
+        }
         lds_barrier();
+
+        // ---------------- D: FENE-P on plane q-2 (own node, component-0 threads) ----------
+        // (independent of C: it reads C - I and u from LDS and writes only Dn)
+        auto phase_d = [&]() {
+            if (fene && q >= z0 + 2 && active) {
+                const int t = wrapn(q - 2, nz);
+                const int st = ((q - 2) % 3 + 3) % 3;
+                const int st1 = ((q - 1) % 3 + 3) % 3;
+                float d0[6], u0[3];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) d0[k] = L.cs[st][k][oi2];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) u0[d] = L.u[st][d][oi1];
+                float Gm[3][3];
+                float adv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    float up[3], um[3];
+                    if (i == 2) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            up[d] = L.u[st1][d][oi1];
+                            um[d] = u_old[d];
+                        }
+                    } else {
+                        const int off = i == 0 ? 1 : T::W1;
+                        const bool top = i == 1 && ogy == ny - 1;
+                        const bool bot = i == 1 && ogy == 0;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const float vp = L.u[st][d][oi1 + off];
+                            const float vm = L.u[st][d][oi1 - off];
+                            up[d] = top ? 2.0f * p.ut[d] - u0[d] : vp;
+                            um[d] = bot ? 2.0f * p.ub[d] - u0[d] : vm;
+                        }
+                    }
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) Gm[i][d] = 0.5f * (up[d] - um[d]);
+                    float dn[6];
+                    const bool bwd = u0[i] >= 0.0f;  // upwind: backward difference for u_i >= 0
+                    if (i == 2) {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) dn[k] = bwd ? c_old[k] : L.cs[st1][k][oi2];
+                    } else {
+                        const int off = i == 0 ? 1 : T::W2;
+                        const int in = bwd ? oi2 - off : oi2 + off;
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) dn[k] = L.cs[st][k][in];
+                    }
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) adv[k] += bwd ? u0[i] * (d0[k] - dn[k]) : u0[i] * (dn[k] - d0[k]);
+                }
+                const float trd = d0[0] + d0[1] + d0[2];
+                const float den = p.L2m3 - trd;
+                if (!(den > 0.0f)) bad |= 2u;
+                const float inv = 1.0f / den;
+                const float f = p.L2m3 * inv;
+                const float fm1 = trd * inv;
+                float dnew[6];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                    for (int b = a; b < 3; ++b) {
+                        const int kk = sidx(a, b);
+                        float stv = Gm[b][a] + Gm[a][b];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) stv += Gm[k][a] * d0[sidx(k, b)] + d0[sidx(a, k)] * Gm[k][b];
+                        const float relax = (f * d0[kk] + (a == b ? fm1 : 0.0f)) * p.inv_tau_p;
+                        dnew[kk] = d0[kk] + (-adv[kk] + stv - relax);
+                    }
+                }
+                const uint32_t bt = ((uint32_t)t * plane + own_xy) * 4u;
+                float check = 0.0f;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    st_off(Dn + (size_t)k * N, bt, dnew[k]);
+                    check += dnew[k];
+                }
+                if (!isfinite(check)) bad |= 1u;
+                const float c0 = 1.0f + dnew[0], c1 = 1.0f + dnew[1], c2 = 1.0f + dnew[2];
+                if (!(c0 + c1 + c2 < p.L2)) bad |= 2u;
+                const float m2 = c0 * c1 - dnew[3] * dnew[3];
+                const float m3 = c0 * (c1 * c2 - dnew[5] * dnew[5]) - dnew[3] * (dnew[3] * c2 - dnew[5] * dnew[4]) +
+                                 dnew[4] * (dnew[3] * dnew[5] - c1 * dnew[4]);
+                if (!(c0 > 0.0f && m2 > 0.0f && m3 > 0.0f)) bad |= 4u;
+            }
+        };
 
         // ---------------- C: collide + stream plane q-1 (own node, own component) ----------
         // BGK with the forcing source (eq. LB, Lambda = I/tau(phi)), per opposite pair.
@@ -578,7 +773,13 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
         // from x - c_x, taken from the neighbouring lane of its row; the edge lane of a row
         // collides the halo node's inbound directions itself (same arithmetic, same inputs),
         // so every row of every direction is written as whole lines by one workgroup.
-        if (q >= z0 + 1 && q <= z1 && ogy < ny) {
+        // MO also collides the planes z0-1 and z1 (no stores) and a neighbouring row.
+        const bool cplane = MO ? (q >= z0 && q <= z1 + 1) : (q >= z0 + 1 && q <= z1);
+        const bool store = q >= z0 + 1 && q <= z1;
+        const bool own_ok = ogy < ny;
+        float up[4] = {0.f, 0.f, 0.f, 0.f}, dn[4] = {0.f, 0.f, 0.f, 0.f}, hj[4] = {0.f, 0.f, 0.f, 0.f};
+        if (MO) phase_d();
+        if (cplane && (own_ok || (MO && hrow != 0))) {
             const int sr = ((q - 1) % 3 + 3) % 3;
             const int p2 = s2 ^ 1;
             const int r = wrapn(q - 1, nz);
@@ -588,34 +789,43 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
             const uint32_t zrow[3] = {(uint32_t)(r == 0 ? nz - 1 : r - 1) * plane, (uint32_t)r * plane,
                                       (uint32_t)(r + 1 == nz ? 0 : r + 1) * plane};
             const uint32_t bself = (zrow[1] + yrow + xcol[1]) * 4u;
-            float hpop[kQ];
-            if constexpr (TP) {
-#pragma unroll
-                for (int a = 0; a < kQ; ++a) hpop[a] = ld_off(hs + (size_t)a * N, bself);
-            } else {
-#pragma unroll
-                for (int a = 0; a < kQ; ++a) hpop[a] = L.pop[TP ? 0 : p2][TP ? 0 : comp][a][TP ? 0 : nid];
-            }
             // the halo nodes' post-collision values that stream into this row's edge nodes:
             // lane m < 5 of the row collides direction xpair(m) (c_x = +1) of the left halo
-            // node, lane 5 + m direction xpair(m) + 1 (c_x = -1) of the right one
+            // node, lane 5 + m direction xpair(m) + 1 (c_x = -1) of the right one.  MO: lanes
+            // 10 and 11 collide the diagonal that enters the tile's corner from the corner
+            // node of the neighbouring row (left: c_x = +1, right: c_x = -1)
             float hval = 0.0f;
-            if (olx < 10) {
-                const bool lside = olx < 5;
-                const int m = lside ? olx : olx - 5;
-                const int ap = m == 0 ? 1 : 5 + 2 * m;  // xpair(m)
+            const bool e_own = own_ok && olx < 10;
+            const bool e_corner = MO && hrow != 0 && (olx == 10 || olx == 11);
+            if (e_own || e_corner) {
+                int ap, nlx, nly;
+                bool take_a;
+                if (e_own) {
+                    const bool lside = olx < 5;
+                    const int m = lside ? olx : olx - 5;
+                    ap = m == 0 ? 1 : 5 + 2 * m;  // xpair(m)
+                    take_a = lside;
+                    nlx = lside ? -1 : txe;
+                    nly = oly;
+                } else {
+                    const bool left = olx == 10;
+                    ap = ((hrow < 0) == left) ? 7 : 9;
+                    take_a = left;
+                    nlx = left ? -1 : txe;
+                    nly = hrow;
+                }
                 const float ex = 1.0f;
                 const float ey = ap == 7 ? 1.0f : (ap == 9 ? -1.0f : 0.0f);
                 const float ez = ap == 11 ? 1.0f : (ap == 13 ? -1.0f : 0.0f);
                 const float w = ap == 1 ? wgt(1) : wgt(7);
-                const int dl = lside ? -1 - olx : txe - olx;  // halo column relative to this lane
-                const uint32_t hx = (uint32_t)wrapn(lside ? x0 - 1 : x0 + txe, nx);  // halo column
-                const uint32_t bo = (zrow[1] + yrow + hx) * 4u;
-                const float hv = ld_off(hs + (size_t)(lside ? ap : ap + 1) * N, bo);
-                const CollideIn in = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, oi1 + dl, oi2 + dl);
+                const uint32_t hx = (uint32_t)wrapn(x0 + nlx, nx);  // halo column
+                const uint32_t bo = (zrow[1] + (uint32_t)(y0 + nly) * (uint32_t)nx + hx) * 4u;
+                const float hv = ld_off(hs + (size_t)(take_a ? ap : ap + 1) * N, bo);
+                const CollideIn in = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, (nly + 1) * T::W1 + nlx + 1,
+                                                                (nly + 2) * T::W2 + nlx + 2);
                 float pa, pb;
                 collide_pair_c(in, ex, ey, ez, w, hv, hv, pa, pb);
-                hval = lside ? pa : pb;
+                hval = take_a ? pa : pb;
             }
             float lin[5], rin[5];
 #pragma unroll
@@ -623,128 +833,119 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 lin[m] = __shfl(hval, m, TX);
                 rin[m] = __shfl(hval, 5 + m, TX);
             }
-            const CollideIn own = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, oi1, oi2);
-            const bool stx = ogx < nx;  // lanes past a ragged edge compute but do not store
-            float check;
-            {
-                const float post = collide_rest(own, hpop[0]);
-                if (stx) st_off(hns, bself, post);
-                check = post;
+            float cl = 0.0f, cr = 0.0f;
+            if constexpr (MO) {
+                cl = __shfl(hval, 10, TX);
+                cr = __shfl(hval, 11, TX);
             }
+            if (own_ok) {
+                float hpop[kQ];
+                if constexpr (TP) {
 #pragma unroll
-            for (int a = 1; a < kQ; a += 2) {
-                float pp, pm;
-                collide_pair(own, a, hpop[a], hpop[a + 1], pp, pm);
-                check += pp + pm;
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const int bq = a + e;
-                    const float post = e == 0 ? pp : pm;
-                    float v = post;
-                    if (cx(bq) > 0) {
-                        v = __shfl_up(post, 1, TX);
-                        if (left_edge) v = lin[xpair_index(a)];
-                    } else if (cx(bq) < 0) {
-                        v = __shfl_down(post, 1, TX);
-                        if (right_edge) v = rin[xpair_index(a)];
-                    }
-                    const int yd = ogy + cy(bq);
-                    if (yd >= 0 && yd < ny) {
-                        const uint32_t dst = zrow[cz(bq) + 1] + yrow + (uint32_t)(cy(bq) * nx) + xcol[1];
-                        if (stx) st_off(hns + (size_t)bq * N, dst * 4u, v);
-                    } else if (stx) {
-                        // moving-wall bounce-back (Sec. 3.1 walls): the link returns as opp(bq)
-                        const float* uw = yd < 0 ? p.ub : p.ut;
-                        const float cuw = cx(bq) * uw[0] + cz(bq) * uw[2];
-                        st_off(hns + (size_t)opp(bq) * N, bself, post - 6.0f * wgt(bq) * own.rs * cuw);
-                    }
-                }
-            }
-            if (stx && !isfinite(check)) bad |= 1u;
-        }
-        // ---------------- D: FENE-P on plane q-2 (own node, component-0 threads) ----------
-        if (fene && q >= z0 + 2 && active) {
-            const int t = wrapn(q - 2, nz);
-            const int st = ((q - 2) % 3 + 3) % 3;
-            const int st1 = ((q - 1) % 3 + 3) % 3;
-            float d0[6], u0[3];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) d0[k] = L.cs[st][k][oi2];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) u0[d] = L.u[st][d][oi1];
-            float Gm[3][3];
-            float adv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                float up[3], um[3];
-                if (i == 2) {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        up[d] = L.u[st1][d][oi1];
-                        um[d] = u_old[d];
-                    }
+                    for (int a = 0; a < kQ; ++a) hpop[a] = ld_off(hs + (size_t)a * N, bself);
                 } else {
-                    const int off = i == 0 ? 1 : T::W1;
-                    const bool top = i == 1 && ogy == ny - 1;
-                    const bool bot = i == 1 && ogy == 0;
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const float vp = L.u[st][d][oi1 + off];
-                        const float vm = L.u[st][d][oi1 - off];
-                        up[d] = top ? 2.0f * p.ut[d] - u0[d] : vp;
-                        um[d] = bot ? 2.0f * p.ub[d] - u0[d] : vm;
+                    for (int a = 0; a < kQ; ++a) hpop[a] = L.pop[TP ? 0 : p2][TP ? 0 : comp][a][TP ? 0 : nid];
+                }
+                const CollideIn own = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, oi1, oi2);
+                const bool stx = ogx < nx;  // lanes past a ragged edge compute but do not store
+                float xv[kQ];               // MO: values leaving the row (c_y != 0), as stored
+                float check;
+                {
+                    const float post = collide_rest(own, hpop[0]);
+                    if (store && stx) st_off(hns, bself, post);
+                    check = post;
+                    if constexpr (MO) add_moments(m0, 0, post);
+                }
+#pragma unroll
+                for (int a = 1; a < kQ; a += 2) {
+                    float pp, pm;
+                    collide_pair(own, a, hpop[a], hpop[a + 1], pp, pm);
+                    check += pp + pm;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int bq = a + e;
+                        const float post = e == 0 ? pp : pm;
+                        float v = post;
+                        if (cx(bq) > 0) {
+                            v = __shfl_up(post, 1, TX);
+                            if (left_edge) v = lin[xpair_index(a)];
+                        } else if (cx(bq) < 0) {
+                            v = __shfl_down(post, 1, TX);
+                            if (right_edge) v = rin[xpair_index(a)];
+                        }
+                        const int yd = ogy + cy(bq);
+                        if (yd >= 0 && yd < ny) {
+                            const uint32_t dst = zrow[cz(bq) + 1] + yrow + (uint32_t)(cy(bq) * nx) + xcol[1];
+                            if (store && stx) st_off(hns + (size_t)bq * N, dst * 4u, v);
+                            if constexpr (MO) {
+                                if (cy(bq) != 0) xv[bq] = v;
+                                else if (cz(bq) > 0) add_moments(mp, bq, v);
+                                else if (cz(bq) < 0) add_moments(mm, bq, v);
+                                else add_moments(m0, bq, v);
+                            }
+                        } else {
+                            // moving-wall bounce-back (Sec. 3.1 walls): the link returns as opp(bq)
+                            const float* uw = yd < 0 ? p.ub : p.ut;
+                            const float bb = post - 6.0f * wgt(bq) * own.rs * wall_cu(bq, uw);
+                            if (store && stx) st_off(hns + (size_t)opp(bq) * N, bself, bb);
+                            if constexpr (MO) {
+                                add_moments(m0, opp(bq), bb);
+                                xv[bq] = 0.0f;
+                            }
+                        }
                     }
                 }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) Gm[i][d] = 0.5f * (up[d] - um[d]);
-                float dn[6];
-                const bool bwd = u0[i] >= 0.0f;  // upwind: backward difference for u_i >= 0
-                if (i == 2) {
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) dn[k] = bwd ? c_old[k] : L.cs[st1][k][oi2];
-                } else {
-                    const int off = i == 0 ? 1 : T::W2;
-                    const int in = bwd ? oi2 - off : oi2 + off;
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) dn[k] = L.cs[st][k][in];
-                }
-#pragma unroll
-                for (int k = 0; k < 6; ++k) adv[k] += bwd ? u0[i] * (d0[k] - dn[k]) : u0[i] * (dn[k] - d0[k]);
-            }
-            const float trd = d0[0] + d0[1] + d0[2];
-            const float den = p.L2m3 - trd;
-            if (!(den > 0.0f)) bad |= 2u;
-            const float inv = 1.0f / den;
-            const float f = p.L2m3 * inv;
-            const float fm1 = trd * inv;
-            float dnew[6];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-#pragma unroll
-                for (int b = a; b < 3; ++b) {
-                    const int kk = sidx(a, b);
-                    float stv = Gm[b][a] + Gm[a][b];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) stv += Gm[k][a] * d0[sidx(k, b)] + d0[sidx(a, k)] * Gm[k][b];
-                    const float relax = (f * d0[kk] + (a == b ? fm1 : 0.0f)) * p.inv_tau_p;
-                    dnew[kk] = d0[kk] + (-adv[kk] + stv - relax);
+                if (store && stx && !isfinite(check)) bad |= 1u;
+                if constexpr (MO) {
+                    fold_up(xv[3], xv[7], xv[10], xv[15], xv[17], up);
+                    fold_dn(xv[4], xv[8], xv[9], xv[16], xv[18], dn);
                 }
             }
-            const uint32_t bt = ((uint32_t)t * plane + own_xy) * 4u;
-            float check = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                st_off(Dn + (size_t)k * N, bt, dnew[k]);
-                check += dnew[k];
+            if constexpr (MO) {
+                // the neighbouring row's directions that enter the tile, x-aligned like the
+                // own stores (lane 0 / the last lane take the corner values of lanes 10 / 11)
+                if (hrow != 0) {
+                    const int hy = hrow;
+                    const uint32_t bh = (zrow[1] + (uint32_t)(y0 + hy) * (uint32_t)nx + xcol[1]) * 4u;
+                    const CollideIn hin = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, (hy + 1) * T::W1 + olx + 1,
+                                                                     (hy + 2) * T::W2 + olx + 2);
+                    float junk;
+                    if (hy < 0) {
+                        const float h3 = ld_off(hs + (size_t)3 * N, bh), h7 = ld_off(hs + (size_t)7 * N, bh);
+                        const float h10 = ld_off(hs + (size_t)10 * N, bh), h15 = ld_off(hs + (size_t)15 * N, bh);
+                        const float h17 = ld_off(hs + (size_t)17 * N, bh);
+                        float v3, v7, v10, v15, v17;
+                        collide_pair(hin, 3, h3, h3, v3, junk);
+                        collide_pair(hin, 7, h7, h7, v7, junk);
+                        collide_pair(hin, 9, h10, h10, junk, v10);
+                        collide_pair(hin, 15, h15, h15, v15, junk);
+                        collide_pair(hin, 17, h17, h17, v17, junk);
+                        float s7 = __shfl_up(v7, 1, TX);
+                        if (left_edge) s7 = cl;
+                        float s10 = __shfl_down(v10, 1, TX);
+                        if (right_edge) s10 = cr;
+                        fold_up(v3, s7, s10, v15, v17, hj);
+                    } else {
+                        const float h4 = ld_off(hs + (size_t)4 * N, bh), h8 = ld_off(hs + (size_t)8 * N, bh);
+                        const float h9 = ld_off(hs + (size_t)9 * N, bh), h16 = ld_off(hs + (size_t)16 * N, bh);
+                        const float h18 = ld_off(hs + (size_t)18 * N, bh);
+                        float v4, v8, v9, v16, v18;
+                        collide_pair(hin, 3, h4, h4, junk, v4);
+                        collide_pair(hin, 7, h8, h8, junk, v8);
+                        collide_pair(hin, 9, h9, h9, v9, junk);
+                        collide_pair(hin, 15, h16, h16, junk, v16);
+                        collide_pair(hin, 17, h18, h18, junk, v18);
+                        float s9 = __shfl_up(v9, 1, TX);
+                        if (left_edge) s9 = cl;
+                        float s8 = __shfl_down(v8, 1, TX);
+                        if (right_edge) s8 = cr;
+                        fold_dn(v4, s8, s9, v16, v18, hj);
+                    }
+                }
             }
-            if (!isfinite(check)) bad |= 1u;
-            const float c0 = 1.0f + dnew[0], c1 = 1.0f + dnew[1], c2 = 1.0f + dnew[2];
-            if (!(c0 + c1 + c2 < p.L2)) bad |= 2u;
-            const float m2 = c0 * c1 - dnew[3] * dnew[3];
-            const float m3 = c0 * (c1 * c2 - dnew[5] * dnew[5]) - dnew[3] * (dnew[3] * c2 - dnew[5] * dnew[4]) +
-                             dnew[4] * (dnew[3] * dnew[5] - c1 * dnew[4]);
-            if (!(c0 > 0.0f && m2 > 0.0f && m3 > 0.0f)) bad |= 4u;
         }
+        if (!MO) phase_d();
 
         // plane q-2 becomes plane q-3 of the next iteration (C and D write no LDS; the
         // barrier after these reads protects the slots the next phase A overwrites)
@@ -756,6 +957,97 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
             for (int d = 0; d < 3; ++d) u_old[d] = L.u[st][d][oi1];
         }
         lds_barrier();
+
+        if constexpr (MO) {
+            // ---------------- exchange: partial moments for the rows above and below ------
+            if (cplane) {
+                const int cb = comp * 8;
+                if (own_ok) {
+                    if (oly + 1 < TY) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) L.X[((cb + k) * TY + oly + 1) * TX + olx] = up[k];
+                    }
+                    if (oly >= 1) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) L.X[((cb + 4 + k) * TY + oly - 1) * TX + olx] = dn[k];
+                    }
+                }
+                if (hrow < 0) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) L.X[(cb + k) * TY * TX + olx] = hj[k];
+                } else if (hrow == TY) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) L.X[((cb + 4 + k) * TY + TY - 1) * TX + olx] = hj[k];
+                }
+            }
+            lds_barrier();
+            if (cplane) {
+                const int cb = comp * 8;
+                if (own_ok && ogy >= 1) {  // from the row below (c_y = +1)
+                    float o[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) o[k] = L.X[((cb + k) * TY + oly) * TX + olx];
+                    m0[0] += o[0];
+                    m0[1] += o[1];
+                    m0[2] += o[0];
+                    mp[0] += o[2];
+                    mp[2] += o[2];
+                    mp[3] += o[2];
+                    mm[0] += o[3];
+                    mm[2] += o[3];
+                    mm[3] -= o[3];
+                }
+                if (own_ok && ogy + 1 < ny) {  // from the row above (c_y = -1)
+                    float o[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) o[k] = L.X[((cb + 4 + k) * TY + oly) * TX + olx];
+                    m0[0] += o[0];
+                    m0[1] += o[1];
+                    m0[2] -= o[0];
+                    mp[0] += o[2];
+                    mp[2] -= o[2];
+                    mp[3] += o[2];
+                    mm[0] += o[3];
+                    mm[2] -= o[3];
+                    mm[3] -= o[3];
+                }
+                // plane q-2 has received all its populations
+                const int t = q - 2;
+                if (t >= z0 && t < z1) {
+                    const int tw = wrapn(t, nz);
+                    if (active) st_off(mom_out + (size_t)comp * N, ((uint32_t)tw * plane + own_xy) * 4u, mm[0]);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) jd[d] = mm[d + 1];
+                    td = tw;
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    mm[k] = m0[k];
+                    m0[k] = mp[k];
+                    mp[k] = 0.0f;
+                }
+            }
+        }
+    }
+    if constexpr (MO) {
+        // the last completed plane's momentum (td is the same in every thread)
+        if (td >= 0) {
+            lds_barrier();
+            if (NC == 2 && comp == NC - 1 && active) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) L.X[T::NFO + d * T::NT + nid] = jd[d];
+            }
+            lds_barrier();
+            if (comp == 0 && active) {
+                const uint32_t bt = ((uint32_t)td * plane + own_xy) * 4u;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    float jv = jd[d];
+                    if (NC == 2) jv += L.X[T::NFO + d * T::NT + nid];
+                    st_off(mom_out + (size_t)(NC + d) * N, bt, jv);
+                }
+            }
+        }
     }
     if (bad) atomicOr(flags, bad);
 }
@@ -772,8 +1064,8 @@ __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused(
     int tx_i, ty_i, zc_i;
     tile_of_block(blockIdx.x, gridDim.x, ntx, nty, gxw, gyh, tx_i, ty_i, zc_i);
     const int z0 = zc_i * zchunk;
-    fused_tile<NC, TX, TY, false>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0, min(z0 + zchunk, p.nz),
-                                  nullptr);
+    fused_tile<NC, TX, TY, false, false>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0,
+                                         min(z0 + zchunk, p.nz), nullptr, nullptr);
 }
 
 // Second pass of the two-pass step: the moments of the whole lattice at time level n are
@@ -791,7 +1083,28 @@ __global__ __launch_bounds__(NC* TX* TY, NC == 2 ? 4 : 2) void k_fused2(
     int tx_i, ty_i, zc_i;
     tile_of_block(blockIdx.x, gridDim.x, ntx, nty, gxw, gyh, tx_i, ty_i, zc_i);
     const int z0 = zc_i * zchunk;
-    fused_tile<NC, TX, TY, true>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0, min(z0 + zchunk, p.nz), mom);
+    fused_tile<NC, TX, TY, true, false>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0,
+                                        min(z0 + zchunk, p.nz), mom, nullptr);
+}
+
+// Chained two-pass step: the second pass of step n, which also writes the moments of
+// level n+1 to `mom_out`, so that step n+1 starts from them without a moments pass.
+// 64x8 tiles only (one tile row per wavefront); 156 KB of LDS for two components.
+template <int NC>
+__global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3(
+    DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
+    float* __restrict__ Dn, const float* __restrict__ mom, float* __restrict__ mom_out, unsigned* __restrict__ flags,
+    int zchunk) {
+    constexpr int TX = 64, TY = 8;
+    __shared__ FusedTile<NC, TX, TY, true, true> L;
+    const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
+    const int gxw = min(ntx, 256 / TX);
+    const int gyh = min(nty, max(1, 32 / gxw));
+    int tx_i, ty_i, zc_i;
+    tile_of_block(blockIdx.x, gridDim.x, ntx, nty, gxw, gyh, tx_i, ty_i, zc_i);
+    const int z0 = zc_i * zchunk;
+    fused_tile<NC, TX, TY, true, true>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0,
+                                       min(z0 + zchunk, p.nz), mom, mom_out);
 }
 
 // Many independent lattices in one launch: each workgroup takes one entry of the work
@@ -807,8 +1120,8 @@ __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused_batch(
     const BatchInstance& bi = inst[w.inst];
     const DevParams p = bi.p;
     const int c = bi.cur ^ parity;
-    fused_tile<NC, TX, TY, false>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0, w.z0, w.z1,
-                                  nullptr);
+    fused_tile<NC, TX, TY, false, false>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0,
+                                         w.z0, w.z1, nullptr, nullptr);
 }
 
 template <int NC, int TX, int TY>
@@ -841,6 +1154,21 @@ hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, 
     if (t.tile == 2) return launch_fused2_t<1, 16, 16>(p, b, zc, s);
     if (t.tile == 3) return launch_fused2_t<1, 64, 8>(p, b, zc, s);
     return launch_fused2_t<1, 32, 8>(p, b, zc, s);
+}
+
+template <int NC>
+static hipError_t launch_fused3_t(const DevParams& p, const Buffers& b, int zchunk, hipStream_t s) {
+    const int ntx = (p.nx + 63) / 64, nty = (p.ny + 7) / 8;
+    const int nzc = (p.nz + zchunk - 1) / zchunk;
+    const int64_t nblk = (int64_t)ntx * nty * nzc;
+    hipLaunchKernelGGL((k_fused3<NC>), dim3((unsigned)nblk), dim3(NC * 64 * 8), 0, s, p, b.h, b.hn, b.D, b.Dn, b.mom,
+                       b.mom_next, b.flags, zchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused3(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s) {
+    const int zc = t.zchunk > 0 ? t.zchunk : p.nz;
+    return p.nc == 2 ? launch_fused3_t<2>(p, b, zc, s) : launch_fused3_t<1>(p, b, zc, s);
 }
 
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,

@@ -22,7 +22,7 @@ constexpr uint64_t kAlign = 256;
 inline uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t h0, h1, D0, D1, mom, uF, stage, red, red_out, flags, total;
+    uint64_t h0, h1, D0, D1, mom, mom2, uF, stage, red, red_out, flags, total;
     int64_t stage_nodes, red_blocks;
 };
 
@@ -53,6 +53,7 @@ Layout layout(const lbfd_grid* g) {
     L.D0 = take((uint64_t)6 * N * 4);
     L.D1 = take((uint64_t)6 * N * 4);
     L.mom = take((uint64_t)(nc + 3) * N * 4);
+    L.mom2 = take((uint64_t)(nc + 3) * N * 4);
     L.uF = take((uint64_t)(3 + 3 * nc) * N * 4);
     L.stage = take((uint64_t)11 * L.stage_nodes * 8);
     L.red = take((uint64_t)L.red_blocks * kDiagVals * 8);
@@ -143,11 +144,23 @@ void bind_current(lbfd_ctx* c) {
     c->buf.hn = c->hbuf[1 - c->cur];
     c->buf.D = c->Dbuf[c->cur];
     c->buf.Dn = c->Dbuf[1 - c->cur];
+    c->buf.mom = c->mbuf[c->mcur];
+    c->buf.mom_next = c->mbuf[1 - c->mcur];
+}
+
+// moments of the current state in buf.mom: kept when they are already there (the chained
+// step carries them from step to step, and recomputing them here would round them
+// differently), else formed by the moments pass
+hipError_t ensure_moments(lbfd_ctx* c) {
+    if (c->mom_valid) return hipSuccess;
+    hipError_t e = launch_moments(c->dp, c->buf, c->stream);
+    if (e == hipSuccess) c->mom_valid = true;
+    return e;
 }
 
 // derived side fields (moments, forces, half-force velocity) of the current state
 hipError_t compute_side_fields(lbfd_ctx* c) {
-    hipError_t e = launch_moments(c->dp, c->buf, c->stream);
+    hipError_t e = ensure_moments(c);
     if (e != hipSuccess) return e;
     return launch_forces(c->dp, c->buf, c->stream);
 }
@@ -177,6 +190,12 @@ hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
             if (tt.zchunk <= 0) tt.zchunk = auto_zchunk(c->grid, tt.tile);
             e = launch_moments(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_fused2(c->dp, c->buf, tt, c->stream);
+        } else if (c->tune.path == LBFD_PATH_CHAINED) {
+            Tuning tt = c->tune;
+            tt.tile = LBFD_TILE_64x8;
+            if (tt.zchunk <= 0) tt.zchunk = auto_zchunk(c->grid, tt.tile);
+            e = ensure_moments(c);
+            if (e == hipSuccess) e = launch_fused3(c->dp, c->buf, tt, c->stream);
         } else {
             Tuning tt = c->tune;
             if (tt.zchunk <= 0) tt.zchunk = auto_zchunk(c->grid, tt.tile);
@@ -184,6 +203,12 @@ hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
         }
         if (e != hipSuccess) return e;
         c->cur = 1 - c->cur;
+        if (c->tune.path == LBFD_PATH_CHAINED) {
+            c->mcur = 1 - c->mcur;  // the step wrote the moments of the new level
+            c->mom_valid = true;
+        } else {
+            c->mom_valid = false;
+        }
         bind_current(c);
         c->steps++;
     }
@@ -267,7 +292,10 @@ lbfd_status lbfd_create(const lbfd_grid* grid, const lbfd_params* params, void* 
     c->Dbuf[0] = (float*)(c->dev + L.D0);
     c->Dbuf[1] = (float*)(c->dev + L.D1);
     c->cur = 0;
-    c->buf.mom = (float*)(c->dev + L.mom);
+    c->mbuf[0] = (float*)(c->dev + L.mom);
+    c->mbuf[1] = (float*)(c->dev + L.mom2);
+    c->mcur = 0;
+    c->mom_valid = false;
     c->buf.uF = (float*)(c->dev + L.uF);
     c->buf.stage = (double*)(c->dev + L.stage);
     c->buf.stage_nodes = L.stage_nodes;
@@ -342,6 +370,7 @@ lbfd_status lbfd_set_fields_box(lbfd_ctx* c, int32_t x0, int32_t y0, int32_t z0,
         HIPCHK(c, hipStreamSynchronize(c->stream), "set_fields sync");
     }
     c->have_fields = true;
+    c->mom_valid = false;
     return LBFD_OK;
 }
 
@@ -480,7 +509,7 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
 lbfd_status lbfd_checkpoint_bytes(lbfd_ctx* c, uint64_t* bytes) {
     if (!c || !bytes) return LBFD_EINVAL;
     const int64_t N = c->dp.N;
-    *bytes = 64 + (uint64_t)(c->grid.ncomp * 19 + 6) * N * 4;
+    *bytes = 64 + (uint64_t)(c->grid.ncomp * 19 + 6 + c->grid.ncomp + 3) * N * 4;
     return LBFD_OK;
 }
 
@@ -502,6 +531,11 @@ lbfd_status lbfd_get_state(lbfd_ctx* c, void* host, uint64_t bytes) {
     HIPCHK(c, hipMemcpyAsync(p + 64 + (size_t)c->grid.ncomp * 19 * N * 4, c->buf.D, (size_t)6 * N * 4,
                              hipMemcpyDeviceToHost, c->stream),
            "state download");
+    // the moments of this level, so that a restart continues bitwise like the run it came from
+    HIPCHK(c, ensure_moments(c), "moments");
+    HIPCHK(c, hipMemcpyAsync(p + 64 + (size_t)(c->grid.ncomp * 19 + 6) * N * 4, c->buf.mom,
+                             (size_t)(c->grid.ncomp + 3) * N * 4, hipMemcpyDeviceToHost, c->stream),
+           "state download");
     HIPCHK(c, hipStreamSynchronize(c->stream), "state sync");
     return LBFD_OK;
 }
@@ -522,6 +556,10 @@ lbfd_status lbfd_set_state(lbfd_ctx* c, const void* host, uint64_t bytes) {
     HIPCHK(c, hipMemcpyAsync(c->buf.D, p + 64 + (size_t)c->grid.ncomp * 19 * N * 4, (size_t)6 * N * 4,
                              hipMemcpyHostToDevice, c->stream),
            "state upload");
+    HIPCHK(c, hipMemcpyAsync(c->buf.mom, p + 64 + (size_t)(c->grid.ncomp * 19 + 6) * N * 4,
+                             (size_t)(c->grid.ncomp + 3) * N * 4, hipMemcpyHostToDevice, c->stream),
+           "state upload");
+    c->mom_valid = true;
     HIPCHK(c, launch_clear_flags(c->buf, c->stream), "clear flags");
     HIPCHK(c, hipStreamSynchronize(c->stream), "state sync");
     c->steps = hdr[5];
@@ -532,7 +570,8 @@ lbfd_status lbfd_set_state(lbfd_ctx* c, const void* host, uint64_t bytes) {
 
 lbfd_status lbfd_set_tuning(lbfd_ctx* c, const lbfd_tuning* t) {
     if (!c || !t) return LBFD_EINVAL;
-    if (t->path != LBFD_PATH_FUSED && t->path != LBFD_PATH_SPLIT && t->path != LBFD_PATH_TWOPASS)
+    if (t->path != LBFD_PATH_FUSED && t->path != LBFD_PATH_SPLIT && t->path != LBFD_PATH_TWOPASS &&
+        t->path != LBFD_PATH_CHAINED)
         return fail(c, LBFD_EINVAL, "bad path");
     if (t->tile < LBFD_TILE_32x8 || t->tile > LBFD_TILE_64x8) return fail(c, LBFD_EINVAL, "bad tile");
     if (t->zchunk < 0) return fail(c, LBFD_EINVAL, "zchunk must be >= 0");

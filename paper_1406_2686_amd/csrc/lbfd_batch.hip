@@ -147,6 +147,7 @@ void advance(lbfd_batch* b, int64_t n) {
         if (!b->active[i]) continue;
         lbfd_ctx* c = b->inst[i];
         c->steps += n;
+        c->mom_valid = false;  // the batched step does not carry moments
         if (n & 1) {
             b->cur[i] ^= 1;
             c->cur = b->cur[i];
@@ -426,18 +427,23 @@ lbfd_status lbfd_autotune(lbfd_ctx* c, int32_t reps, lbfd_tuning* best, double* 
     const int zcs[6] = {8, 16, 32, 64, 128, 256};
     Tuning win = c->tune;
     float best_ms = 1e30f;
-    // a trial step writes the other buffer (and the moments scratch) but does not swap,
-    // so the state is unchanged
+    // a trial step writes the other buffers (and the moments of the current level, which it
+    // recomputes) but does not swap, so the state is unchanged
     auto trial = [&](const Tuning& t) -> hipError_t {
         if (t.path == LBFD_PATH_TWOPASS) {
             hipError_t e = launch_moments(c->dp, c->buf, c->stream);
             return e != hipSuccess ? e : launch_fused2(c->dp, c->buf, t, c->stream);
         }
+        if (t.path == LBFD_PATH_CHAINED) {
+            hipError_t e = ensure_moments(c);
+            return e != hipSuccess ? e : launch_fused3(c->dp, c->buf, t, c->stream);
+        }
         return launch_fused(c->dp, c->buf, t, c->stream);
     };
-    for (int path : {LBFD_PATH_TWOPASS, LBFD_PATH_FUSED})
+    for (int path : {LBFD_PATH_CHAINED, LBFD_PATH_TWOPASS, LBFD_PATH_FUSED})
     for (int ti : {LBFD_TILE_32x8, LBFD_TILE_16x16, LBFD_TILE_64x8}) {
-        if (ti == LBFD_TILE_64x8 && path != LBFD_PATH_TWOPASS) continue;
+        if (ti == LBFD_TILE_64x8 && path == LBFD_PATH_FUSED) continue;
+        if (ti != LBFD_TILE_64x8 && path == LBFD_PATH_CHAINED) continue;
         for (int zc : zcs) {
             if (zc > c->grid.nz && zc != 8) continue;
             Tuning t{path, ti, std::min(zc, c->grid.nz)};

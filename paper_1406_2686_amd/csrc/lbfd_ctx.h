@@ -17,7 +17,10 @@ struct lbfd_ctx {
     lbfd::Tuning tune;
     float* hbuf[2];
     float* Dbuf[2];
+    float* mbuf[2];    // moments of two levels (the chained step reads one, writes the other)
     int cur;
+    int mcur;          // mbuf[mcur] holds the moments of the current level when mom_valid
+    bool mom_valid;
     hipStream_t stream;
     int device;
     char* dev;
@@ -30,6 +33,7 @@ struct lbfd_ctx {
 
 namespace lbfd {
 hipError_t compute_side_fields(lbfd_ctx* c);
+hipError_t ensure_moments(lbfd_ctx* c);
 int auto_zchunk(const lbfd_grid& g, int tile);
 hipError_t enqueue_steps(lbfd_ctx* c, int64_t n);
 hipError_t read_flags(lbfd_ctx* c, unsigned* out);

@@ -30,7 +30,8 @@ struct Buffers {
     float* hn;         // populations at n+1
     float* D;          // C - I at time n: [6][N]
     float* Dn;         // C - I at n+1
-    float* mom;        // side field: [nc+3][N] = delta rho_A, (delta rho_B), j_x, j_y, j_z
+    float* mom;        // side field: [nc+3][N] = delta rho_A, (delta rho_B), j_x, j_y, j_z (level n)
+    float* mom_next;   // the same at level n+1, written by the chained step
     float* uF;         // side field: [3+3nc][N] = u (half-force), F_A, (F_B)
     double* stage;     // FP64 staging for host transfers: 11 x stage_nodes
     int64_t stage_nodes;
@@ -81,6 +82,8 @@ hipError_t launch_set_flags(const Buffers& b, unsigned v, hipStream_t s);
 hipError_t launch_fused(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
 // second pass of the two-pass step (after launch_moments over the same time level)
 hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
+// chained two-pass step: launch_fused2's work plus the moments of level n+1 (b.mom -> b.mom_next)
+hipError_t launch_fused3(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,
                               int parity, hipStream_t s);
 void fused_tile_shape(int ncomp, int tile, int* tx, int* ty);

@@ -287,6 +287,106 @@ def test_two_pass_step_matches_oracle(lb, case):
     assert abs(dg["D"] - do["D"]) < 1e-5
 
 
+def test_chained_launch_shapes_agree_bitwise_and_match_two_pass(lb):
+    """The chained step (the second pass also forms the next level's moments) sums the
+    same values in the same order for every z-chunk, including one plane per workgroup,
+    where every plane is also collided as a neighbour of two chunks: results are bitwise
+    identical across z-chunks.  Against the two-pass step (moments from a separate pass,
+    summed in another order) they agree to FP32 rounding."""
+    wl = workloads.droplet_shear(nx=45, ny=19, nz=23, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="B", De=0.5, U=0.01)
+    ref = None
+    for zc in (0, 1, 3, 7, 23):
+        lat = lb.from_workload(wl)
+        lat.set_tuning(lb.PATH_CHAINED, "64x8", zc)
+        lat.step(40)
+        f = lat.get_fields()
+        lat.close()
+        if ref is None:
+            ref = f
+        else:
+            for a, b in zip(f, ref):
+                assert np.array_equal(a, b), ("chained", zc)
+    lat = lb.from_workload(wl)
+    lat.set_tuning(lb.PATH_TWOPASS, "64x8", 0)
+    lat.step(40)
+    t = lat.get_fields()
+    lat.close()
+    e = report("chained-vs-two-pass", ref, t)
+    # the moments of every step are FP32 sums in another order: |du| ~ 1e-7 against
+    # |u| ~ 1e-2, a relative L2 of a few 1e-6 after 40 steps
+    assert e["u"] < 5e-6 and e["C"] < 1e-7 and e["rho"] < 1e-7
+
+
+@pytest.mark.parametrize("case", ["cfg1_physics", "couette", "ragged_polyB", "wide_ragged_polyA"])
+def test_chained_step_matches_oracle(lb, case):
+    """The chained step against the FP64 oracle: the full 128x64x128 droplet, the
+    one-component FENE-P Couette, and ragged grids (several 64-wide tiles with a partial
+    one, ny not a multiple of 8, several z-chunks)."""
+    if case == "cfg1_physics":
+        wl, steps = workloads.droplet_cfg1(De=1.0, variant="physics"), 100
+    elif case == "couette":
+        wl, steps = workloads.couette_fenep(), 4000
+    elif case == "ragged_polyB":
+        wl = workloads.droplet_shear(nx=37, ny=21, nz=29, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                     polymer_phase="B", De=0.5, U=0.008)
+        steps = 1500
+    else:
+        wl = workloads.droplet_shear(nx=150, ny=27, nz=20, R=8.0, G=workloads.G_PHYSICS_1_004,
+                                     polymer_phase="A", De=1.0, U=0.01)
+        steps = 300
+    lat = lb.from_workload(wl)
+    lat.set_tuning(lb.PATH_CHAINED, "64x8", 6 if case == "wide_ragged_polyA" else 0)
+    lat.step(steps)
+    g = lat.get_fields()
+    dg = lat.diagnostics()
+    lat.close()
+    o = oracle.from_workload(wl)
+    assert o.step(steps) == 0
+    r = o.get_fields()
+    do = o.diagnostics()
+    e = report(f"chained-{case}", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert abs(dg["D"] - do["D"]) < 1e-5
+
+
+def test_chained_step_restarts_and_diagnostics_bitwise(lb):
+    """The chained step carries the moments from step to step.  Diagnostics and field
+    reads use them without recomputing them, and a checkpoint holds them, so a run with
+    diagnostics, a run without, and a run restarted from a checkpoint agree bitwise."""
+    wl = workloads.droplet_shear(nx=64, ny=32, nz=48, R=8.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="A", De=1.0, U=0.01)
+
+    def chained():
+        lat = lb.from_workload(wl)
+        lat.set_tuning(lb.PATH_CHAINED, "64x8", 0)
+        return lat
+
+    a = chained()
+    d0 = a.diagnostics()
+    for _ in range(5):
+        a.step(100)
+        a.diagnostics()
+    blob = a.get_state()
+    a.step(500)
+    fa = a.get_fields()
+    b = chained()
+    b.step(1000)
+    fb = b.get_fields()
+    c = chained()
+    c.set_state(blob)
+    c.step(500)
+    fc = c.get_fields()
+    d1 = c.diagnostics()
+    for x, y, z in zip(fa, fb, fc):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    assert d1["step"] == 1000
+    for k in ("mass_A", "mass_B"):
+        assert abs(d1[k] - d0[k]) < 1e-6 * d0[k]
+    for lat in (a, b, c):
+        lat.close()
+
+
 def test_full_size_droplet_sampled_window(lb):
     """The 1024x256x1024 droplet (268M nodes) in the launch configuration the benchmark
     times, checked against the oracle on a sampled window.  One step moves information at
