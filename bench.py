@@ -24,23 +24,33 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per node and step (FP32): populations read + written
 # (2 x ncomp x 19 x 4) and C read + written (2 x 6 x 4)
 ALG_BYTES = {1: 200, 2: 352}
-# kernels of one step per launch path (the two-pass step is the default)
+# kernels of one step per launch path (the chained step is the default)
 STEP_KERNELS = {0: "k_fused (one launch per step)", 1: "k_moments + k_forces + k_collide",
-                2: "k_moments + k_fused2 (two launches per step; bytes are the step's minimum)"}
+                2: "k_moments + k_fused2 (two launches per step; bytes are the step's minimum)",
+                3: "k_fused3 (one launch per step; it also forms the next step's moments)"}
+LAUNCHES_PER_STEP = {0: 1, 1: 3, 2: 2, 3: 1}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def recorded_traffic(workload):
+# committed counter summary per launch path (chained: k_fused3, two-pass: k_moments + k_fused2)
+PROFILE_STEM = {2: "k_fused2", 3: "k_fused3"}
+
+
+def recorded_traffic(workload, path_id):
     """HBM bytes per step (the step's launches together) on `workload`, from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
-    reads for a copy of known size).  Returned only while the kernel sources hash to the
-    profiled ones; a changed kernel gives None until it is profiled again."""
+    rocprofv3 counter summary of that launch path (FETCH_SIZE and WRITE_SIZE, each scaled
+    by what the counter reads for a copy of known size).  Returned only while the kernel
+    sources hash to the profiled ones; a changed kernel gives None until it is profiled
+    again."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", f"k_fused_{workload.replace('droplet_shear_', 'droplet_')}.md")
+    if path_id not in PROFILE_STEM:
+        return None
+    path = os.path.join(ROOT, "profiles",
+                        f"{PROFILE_STEM[path_id]}_{workload.replace('droplet_shear_', 'droplet_')}.md")
     if not os.path.exists(path):
         return None
     rec = None
@@ -279,6 +289,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--grid", type=str, default="1024x256x1024")
     ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--path", choices=["default", "chained", "two-pass", "fused", "split"], default="default",
+                    help="launch path of the step (default: the library's, the chained step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="droplet-sweep mode: plain vs batched vs surrogate (with solver fallback) time to steady D")
@@ -324,6 +336,10 @@ def main():
     torch.cuda.synchronize()
     log(f"init {nx}x{ny}x{nz}: {time.perf_counter() - t_init:.1f} s")
 
+    if args.path != "default":
+        pid = {"fused": lb.PATH_FUSED, "split": lb.PATH_SPLIT, "two-pass": lb.PATH_TWOPASS,
+               "chained": lb.PATH_CHAINED}[args.path]
+        lat.set_tuning(pid, "32x8" if pid in (lb.PATH_FUSED, lb.PATH_SPLIT) else "64x8", 0)
     tuning = lat.get_tuning()
     d0 = lat.diagnostics()
     lat.step_async(args.warmup)
@@ -359,7 +375,7 @@ def main():
     mlups = N * K / wall / 1e6
     alg = ALG_BYTES[2] * N
     achieved = alg / (step_ms * 1e-3) / 1e9
-    rec = recorded_traffic(f"droplet_shear_{nx}x{ny}x{nz}")
+    rec = recorded_traffic(f"droplet_shear_{nx}x{ny}x{nz}", tuning["path"])
     traffic = None if rec is None else round(rec["bytes_per_step"] / (step_ms * 1e-3) / 1e9, 1)
     mass_drift = max(abs(d1["mass_A"] - d0["mass_A"]) / d0["mass_A"],
                      abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"])
@@ -369,14 +385,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"droplet_shear_{nx}x{ny}x{nz}", "nodes": N, "ncomp": 2,
-                   "launch": {"path": ["fused", "split", "two-pass"][tuning["path"]], "tile": tuning["tile"],
+                   "launch": {"path": ["fused", "split", "two-pass", "chained"][tuning["path"]], "tile": tuning["tile"],
                               "zchunk": tuning["zchunk"]},
                    "droplet_R": wl0["meta"]["R"], "polymer": "matrix (L2=400, De=1)",
                    "diag_every": args.diag_every, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": STEP_KERNELS.get(tuning["path"], "?"),
-                     "launches_per_step": 2 if tuning["path"] == 2 else (3 if tuning["path"] == 1 else 1),
+                     "launches_per_step": LAUNCHES_PER_STEP[tuning["path"]],
                      "alg_bytes_per_node": ALG_BYTES[2], "event_ms_per_step": round(step_ms, 4),
                      "traffic_bytes_per_step": None if rec is None else rec["bytes_per_step"],
                      "traffic_source": None if rec is None else rec["path"]},

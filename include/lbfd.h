@@ -163,9 +163,9 @@ lbfd_status lbfd_get_state(lbfd_ctx* ctx, void* host, uint64_t bytes);
 lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
 
 /* Launch shape of the step.  path: LBFD_PATH_FUSED (one pass over HBM per step),
- * LBFD_PATH_TWOPASS (the default: a streaming moments pass, then one pass that reads the
- * moments and C with their halos and only the tile's own populations), LBFD_PATH_CHAINED
- * (the two-pass step whose second pass also forms the moments of the next level, so that a
+ * LBFD_PATH_TWOPASS (a streaming moments pass, then one pass that reads the moments and C
+ * with their halos and only the tile's own populations), LBFD_PATH_CHAINED (the default:
+ * the two-pass step whose second pass also forms the moments of the next level, so that a
  * run of steps needs one launch per step and the moments pass runs only when the moments
  * of the current level are not at hand: after set_fields, another path or a batch; 64x8
  * tiles whatever `tile` says) or LBFD_PATH_SPLIT (three passes: moments, forces, collide;

@@ -576,13 +576,14 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     }
 
     for (int q = z0 - 2; q <= z1 + 1; ++q) {
-        // The lane-dependent indices are derived again in every plane from a copy of the
-        // thread index that the compiler cannot see through (an empty asm statement).
-        // Otherwise it keeps every LDS and global address it can form from them live
-        // across the loop.  With 1024 threads per workgroup a thread has 128 VGPRs, and
+        // Two-pass bodies: the lane-dependent indices are derived again in every plane
+        // from a copy of the thread index that the compiler cannot see through (an empty
+        // asm statement).  Otherwise it keeps every LDS and global address it can form
+        // from them live across the loop; at 128 VGPRs per thread (four waves per SIMD)
         // those addresses would be spilled to scratch, whose reloads cost HBM traffic.
+        // The single-pass body runs two waves per SIMD and keeps them in registers.
         int tq = tid;
-        asm volatile("" : "+v"(tq));
+        if constexpr (TP) asm volatile("" : "+v"(tq));
         const int nid = tq % T::NT;
         const int olx = nid % TX, oly = nid / TX;
         const int ogx = x0 + olx, ogy = y0 + oly;

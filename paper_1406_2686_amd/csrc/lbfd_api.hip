@@ -305,10 +305,10 @@ lbfd_status lbfd_create(const lbfd_grid* grid, const lbfd_params* params, void* 
     c->buf.flags = (unsigned*)(c->dev + L.flags);
     bind_current(c);
     fill_devparams(c);
-    // the two-pass step on 64x8 tiles is the fastest shape on large lattices (30.5 ms per
-    // step on the 1024x256x1024 droplet, against 33.1 on 32x8 tiles and 47.2 for the fused
-    // single pass); lbfd_autotune compares the shapes for a given lattice
-    c->tune = Tuning{LBFD_PATH_TWOPASS, LBFD_TILE_64x8, 0};
+    // the chained step is the fastest shape on large lattices (25.5 ms per step on the
+    // 1024x256x1024 droplet, against 30.0 for the two-pass step on the same 64x8 tiles and
+    // 47.2 for the fused single pass); lbfd_autotune compares the shapes for a given lattice
+    c->tune = Tuning{LBFD_PATH_CHAINED, LBFD_TILE_64x8, 0};
     c->steps = 0;
     c->flags_seen = 0;
     c->have_fields = false;
@@ -582,8 +582,8 @@ lbfd_status lbfd_set_tuning(lbfd_ctx* c, const lbfd_tuning* t) {
 lbfd_status lbfd_get_tuning(lbfd_ctx* c, lbfd_tuning* t) {
     if (!c || !t) return LBFD_EINVAL;
     t->path = c->tune.path;
-    t->tile = c->tune.tile;
-    t->zchunk = c->tune.zchunk > 0 ? c->tune.zchunk : auto_zchunk(c->grid, c->tune.tile);
+    t->tile = c->tune.path == LBFD_PATH_CHAINED ? LBFD_TILE_64x8 : c->tune.tile;
+    t->zchunk = c->tune.zchunk > 0 ? c->tune.zchunk : auto_zchunk(c->grid, t->tile);
     t->reserved = 0;
     return LBFD_OK;
 }

@@ -427,12 +427,15 @@ lbfd_status lbfd_autotune(lbfd_ctx* c, int32_t reps, lbfd_tuning* best, double* 
     const int zcs[6] = {8, 16, 32, 64, 128, 256};
     Tuning win = c->tune;
     float best_ms = 1e30f;
-    // a trial step writes the other buffers (and the moments of the current level, which it
-    // recomputes) but does not swap, so the state is unchanged
+    // a trial step writes the other buffers (populations, C and moments of the next level)
+    // but does not swap, so the state is unchanged; the two-pass trials form their moments
+    // in the next level's moments buffer, so that moments carried by the chained step stay
     auto trial = [&](const Tuning& t) -> hipError_t {
         if (t.path == LBFD_PATH_TWOPASS) {
-            hipError_t e = launch_moments(c->dp, c->buf, c->stream);
-            return e != hipSuccess ? e : launch_fused2(c->dp, c->buf, t, c->stream);
+            Buffers tb = c->buf;
+            tb.mom = c->buf.mom_next;
+            hipError_t e = launch_moments(c->dp, tb, c->stream);
+            return e != hipSuccess ? e : launch_fused2(c->dp, tb, t, c->stream);
         }
         if (t.path == LBFD_PATH_CHAINED) {
             hipError_t e = ensure_moments(c);
