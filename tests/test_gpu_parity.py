@@ -387,6 +387,37 @@ def test_chained_step_restarts_and_diagnostics_bitwise(lb):
         lat.close()
 
 
+@pytest.mark.parametrize("Lam,coupling", [(0.625, "force"), (2.5, "force"), (2.5, "stress")])
+def test_gpu_steady_shear_matches_lindner_closed_form(lb, Lam, coupling):
+    """The GPU step against the paper directly, not only against the oracle: plane Couette
+    with feedback on, run for 20 polymer times, gives the closed-form steady-shear
+    conformation C = sigma_P / Z of Sec. 3.1 (eqs. lindner, lindner2) at L^2 = 100, with
+    C_yy = C_zz (no second normal-stress difference) and the linear velocity profile (a
+    uniform stress moves no fluid), in both couplings."""
+    from paper_closed_forms import lindner_N, lindner_S, steady_shear_conformation
+
+    ny, tau_p, L2 = 16, 1000.0 if Lam < 1 else 200.0, 100.0
+    U = Lam / tau_p * ny / 2.0
+    wl = workloads.couette_fenep(nx=2, ny=ny, nz=2, U=U, tau_p=tau_p, L2=L2, noise=0.0, coupling=coupling)
+    wl["params"]["eta_p"] = 1.0 / 24.0
+    lat = lb.from_workload(wl)
+    lat.step(int(20 * tau_p))
+    _, u, C = lat.get_fields()
+    assert lat.flags() == 0
+    lat.close()
+    ref = steady_shear_conformation(Lam, L2)
+    keys = ("xx", "yy", "zz", "xy", "xz", "yz")
+    for k, key in enumerate(keys):
+        assert np.allclose(C[k], ref[key], rtol=5e-5, atol=5e-6), (key, C[k][:4], ref[key])
+    assert np.max(np.abs(C[1] - C[2])) < 1e-6 and np.max(np.abs(C[4:])) < 1e-6
+    tr = C[0] + C[1] + C[2]
+    f = (L2 - 3) / (L2 - tr)
+    assert np.allclose(f * C[3], lindner_S(Lam, L2), rtol=5e-5)
+    assert np.allclose(f * C[0] - 1, lindner_N(Lam, L2), rtol=2e-4)
+    Y = np.repeat(np.arange(ny), 2)[None, :].repeat(2, 0).ravel()
+    assert np.allclose(u[0], -U + 2 * U * (Y + 0.5) / ny, atol=1e-4 * U)
+
+
 def test_full_size_droplet_sampled_window(lb):
     """The 1024x256x1024 droplet (268M nodes) in the launch configuration the benchmark
     times, checked against the oracle on a sampled window.  One step moves information at

@@ -9,7 +9,8 @@ from scipy.integrate import solve_ivp
 
 import oracle
 import workloads
-from paper_closed_forms import cessation_S_ratio, lindner_N, lindner_S, steady_shear_conformation
+from paper_closed_forms import (cessation_S_ratio, elongation_rate, lindner_N, lindner_S, saos_moduli,
+                                steady_shear_conformation)
 
 KEYS = ("xx", "yy", "zz", "xy", "xz", "yz")
 
@@ -142,3 +143,98 @@ def test_cessation_relaxation_follows_closed_forms():
     assert np.allclose(Ss, pred, rtol=4e-3)
     # relaxation of a FENE-P dumbbell is faster than the Oldroyd-B exponential at early times
     assert Ts[0] < T0 * math.exp(-0.25)
+
+
+def centre_probe(u_of_xyz, tau_p, L2):
+    """3x3x3 lattice in kinematic mode with a velocity field that vanishes at the centre node:
+    there the upwind advection term is u . grad C = 0 exactly and the central differences of
+    a linear field give its gradient exactly, so the centre follows the homogeneous FENE-P
+    update (eq. FENE with uniform G) whatever the other nodes do."""
+    n = 3
+    Z, Y, X = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X, Y, Z = X.ravel() - 1.0, Y.ravel() - 1.0, Z.ravel() - 1.0
+    centre = int(np.argmax((X == 0) & (Y == 0) & (Z == 0)))
+    o = oracle.Oracle(n, n, n, 1)
+    o.set_params(polymer_phase="none", eta_p=0.0, tau_p=tau_p, L2=L2)
+    o.set_walls([0, 0, 0], [0, 0, 0])
+    C = np.zeros((6, X.size))
+    C[:3] = 1.0
+    u = u_of_xyz(X, Y, Z)
+    o.set_fields(np.ones((1, X.size)), u, C)
+    return o, centre, (X, Y, Z)
+
+
+@pytest.mark.parametrize("Lam_e", [0.05, 0.4, 0.9, 1.5])
+def test_uniaxial_elongation_matches_closed_form(Lam_e):
+    """Steady uniaxial elongation u = edot (-x/2, -y/2, z) (Sec. 3.2): the stress difference
+    D = sigma_zz - sigma_xx of the steady state satisfies the closed form of eqs. el8, el9,
+    on the '+' branch below D = L^2 - 3 and on the '-' branch above it (here L^2 = 100, so
+    Lambda_e = 0.9 and 1.5 lie on either side of the double root at Lambda_e = 0.97)."""
+    L2, tau_p = 100.0, 50.0
+    ed = Lam_e / tau_p
+
+    def u_of(X, Y, Z):
+        return np.stack([-0.5 * ed * X, -0.5 * ed * Y, ed * Z])
+
+    o, c, (X, Y, Z) = centre_probe(u_of, tau_p, L2)
+    assert o.fenep_kinematic(u_of(X, Y, Z), int(100 * tau_p)) == 0
+    Cc = o.get_C()[:, c]
+    f = (L2 - 3) / (L2 - Cc[:3].sum())
+    D = f * (Cc[2] - Cc[0])
+    branch = "+" if D < L2 - 3 else "-"
+    assert (branch == "+") == (Lam_e < 0.97)
+    assert abs(elongation_rate(D, L2, branch) - Lam_e) < 1e-6 * Lam_e
+    # axisymmetry: C_xx = C_yy, no off-diagonal part
+    assert abs(Cc[0] - Cc[1]) < 1e-12 and np.max(np.abs(Cc[3:])) < 1e-14
+
+
+def test_elongational_viscosity_tends_to_three_at_small_rates():
+    """Trouton limit (Sec. 3.2): eta_e / eta_P = D / Lambda_e -> 3 as Lambda_e -> 0."""
+    L2, tau_p, Lam_e = 100.0, 50.0, 0.002
+    ed = Lam_e / tau_p
+
+    def u_of(X, Y, Z):
+        return np.stack([-0.5 * ed * X, -0.5 * ed * Y, ed * Z])
+
+    o, c, xyz = centre_probe(u_of, tau_p, L2)
+    assert o.fenep_kinematic(u_of(*xyz), int(40 * tau_p)) == 0
+    Cc = o.get_C()[:, c]
+    f = (L2 - 3) / (L2 - Cc[:3].sum())
+    assert abs(f * (Cc[2] - Cc[0]) / Lam_e - 3.0) < 0.01
+
+
+@pytest.mark.parametrize("wt", [0.5, 2.0, 8.0])
+def test_small_amplitude_oscillatory_shear_moduli(wt):
+    """SAOS (Sec. 3.3): prescribed u_x = gamma0 omega cos(omega t) y in the Oldroyd-B limit
+    (L^2 = 1e8).  After the transient, the shear conformation C_xy (= sigma_xy divided by
+    eta_P/tau_P) oscillates as gamma0 (G' sin + G'' cos) with the moduli of eq. modulipred,
+    up to the first-order error of the explicit update (relative O(omega + 1/tau_P)).  The
+    same fit matches the exact periodic solution of that update,
+    x_{n+1} = (1 - 1/tau_P) x_n + gamma0 omega cos(omega n), to the decayed transient."""
+    tau_p, g0 = 2000.0, 0.01
+    w = wt / tau_p
+
+    def u_of(X, Y, Z, k=0):
+        return np.stack([g0 * w * math.cos(w * k) * Y, 0 * Y, 0 * Y])
+
+    o, c, xyz = centre_probe(u_of, tau_p, 1e8)
+    n0 = int(14 * tau_p)
+    n1 = n0 + int(3 * 2 * math.pi / w)
+    ts, xs = [], []
+    for k in range(n1):
+        assert o.fenep_kinematic(u_of(*xyz, k=k), 1) == 0
+        if k >= n0:
+            Cc = o.get_C()[:, c]
+            xs.append(Cc[3])
+            ts.append(k + 1)
+    ts = np.array(ts, dtype=np.float64)
+    A = np.stack([np.sin(w * ts), np.cos(w * ts)], 1)
+    (a, b), *_ = np.linalg.lstsq(A, np.array(xs), rcond=None)
+    Gp, Gpp = saos_moduli(wt)
+    err = 2.0 * (w + 1.0 / tau_p) * (Gp + Gpp)
+    assert abs(a / g0 - Gp) < err and abs(b / g0 - Gpp) < err
+    Z = g0 * w / (np.exp(1j * w) - (1.0 - 1.0 / tau_p))  # x_n = Re(Z e^{i w n})
+    assert abs(a / g0 - (-Z.imag / g0)) < 1e-5 and abs(b / g0 - Z.real / g0) < 1e-5
+    # no normal stress in y, z at first order; C_yy = C_zz = 1 exactly in simple shear
+    Cc = o.get_C()[:, c]
+    assert abs(Cc[1] - 1.0) < 1e-12 and abs(Cc[2] - 1.0) < 1e-12
