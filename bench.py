@@ -219,6 +219,13 @@ def batch_bench(lb, workloads, args):
     wls = [w for i, w in enumerate(wls) if i not in dropped]
     nodes = sum(w["grid"]["nx"] * w["grid"]["ny"] * w["grid"]["nz"] for w in wls)
     b = lb.Batch(wls)
+    if args.path == "chained":
+        b.set_tuning("64x8", 0, path=lb.PATH_CHAINED)
+    elif args.path == "fused":
+        b.set_tuning("32x8", 0, path=lb.PATH_FUSED)
+    elif args.path != "default":
+        raise SystemExit("--batch runs the fused or the chained path")
+    tune = b.get_tuning()
     b.step(args.warmup + args.warmup % 2)
     torch.cuda.synchronize()
     K = args.steps + args.steps % 2
@@ -238,10 +245,13 @@ def batch_bench(lb, workloads, args):
                       "unit": "MLUPS", "n_gpus": 1, "steps": K, "ms_per_step": round(ms, 4), "dtype": "f32",
                       "data": "synthetic", "higher_is_better": True,
                       "config": {"workload": f"{len(wls)} droplet-in-shear lattices, grids x{args.scale} of 64-192 x 32-64",
-                                 "nodes": nodes, "faulting_instances_dropped": dropped},
+                                 "nodes": nodes, "faulting_instances_dropped": dropped,
+                                 "launch": {"path": ["fused", "split", "two-pass", "chained"][tune["path"]],
+                                            "tile": tune["tile"], "zchunk": tune["zchunk"]}},
                       "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                                   "kernel": "k_fused_batch (all instances, one launch per step)"},
+                                   "kernel": ("k_fused3_batch" if tune["path"] == lb.PATH_CHAINED else "k_fused_batch")
+                                   + " (all instances, one launch per step)"},
                       "fault_flags": int(max(x["flags"] for x in d))}), flush=True)
 
 

@@ -222,7 +222,12 @@ lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_para
                               void* dev_state, uint64_t bytes, void* hip_stream, lbfd_batch** out);
 /* Fields of instance i, as lbfd_set_fields. */
 lbfd_status lbfd_batch_set_fields(lbfd_batch* b, int32_t i, const double* rho, const double* u, const double* C);
-/* Fused path only; tile and zchunk as for a single lattice (zchunk >= 4 in a batch). */
+/* path LBFD_PATH_FUSED (the single-pass body; tile and zchunk as for a single lattice,
+ * zchunk >= 4 in a batch) or LBFD_PATH_CHAINED (the chained body on 64x8 tiles: each
+ * instance's moments are carried from step to step; they are formed by the moments pass,
+ * or copied between its two moments buffers, when an instance has none at its current
+ * level).  Results of the two paths agree to FP32 rounding; within a path they do not
+ * depend on the other instances or on tile and zchunk. */
 lbfd_status lbfd_batch_set_tuning(lbfd_batch* b, const lbfd_tuning* t);
 lbfd_status lbfd_batch_get_tuning(lbfd_batch* b, lbfd_tuning* t);
 /* Instances with active[i] == 0 are skipped by lbfd_batch_step (n bytes). */
@@ -238,7 +243,8 @@ lbfd_status lbfd_batch_get_fields(lbfd_batch* b, int32_t i, double* rho, double*
  * are in out[i].flags).  Re-activates every instance before returning. */
 lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit, int64_t max_steps,
                                      lbfd_diag* out, int64_t* steady_step);
-/* Launch-shape autotuner for the batch (state unchanged, as lbfd_autotune). */
+/* Launch-shape autotuner for the batch: both paths, their tiles and a range of z-chunks
+ * (state unchanged, as lbfd_autotune). */
 lbfd_status lbfd_batch_autotune(lbfd_batch* b, int32_t reps, lbfd_tuning* best, double* ms_per_step);
 /* The context of instance i (owned by the batch; valid until lbfd_batch_destroy). */
 lbfd_ctx* lbfd_batch_instance(lbfd_batch* b, int32_t i);

@@ -396,16 +396,25 @@ class Batch:
         C = np.ascontiguousarray(C, dtype=np.float64).reshape(6, N)
         self._check(_lib.lbfd_batch_set_fields(self._h, i, _dp(rho), _dp(u), _dp(C)))
 
-    def set_tuning(self, tile="32x8", zchunk=0):
-        t = Tuning(PATH_FUSED, TILES[tile] if isinstance(tile, str) else int(tile), int(zchunk), 0)
+    def set_tuning(self, tile="32x8", zchunk=0, path=PATH_FUSED):
+        """Launch shape of the batched step: the fused body (tiles 32x8, 16x16) or the
+        chained body (path=PATH_CHAINED, 64x8 tiles)."""
+        t = Tuning(int(path), TILES[tile] if isinstance(tile, str) else int(tile), int(zchunk), 0)
         self._check(_lib.lbfd_batch_set_tuning(self._h, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(_lib.lbfd_batch_get_tuning(self._h, ctypes.byref(t)))
+        inv = {v: k for k, v in TILES.items()}
+        return {"path": int(t.path), "tile": inv[int(t.tile)], "zchunk": int(t.zchunk)}
 
     def autotune(self, reps: int = 3) -> dict:
         t = Tuning()
         ms = ctypes.c_double(0)
         self._check(_lib.lbfd_batch_autotune(self._h, int(reps), ctypes.byref(t), ctypes.byref(ms)))
         inv = {v: k for k, v in TILES.items()}
-        return {"tile": inv[int(t.tile)], "zchunk": int(t.zchunk), "ms_per_step": float(ms.value)}
+        return {"path": int(t.path), "tile": inv[int(t.tile)], "zchunk": int(t.zchunk),
+                "ms_per_step": float(ms.value)}
 
     def set_active(self, active):
         a = (ctypes.c_uint8 * self.n)(*[1 if x else 0 for x in active])

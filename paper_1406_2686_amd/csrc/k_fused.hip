@@ -1125,6 +1125,21 @@ __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused_batch(
                                          w.z0, w.z1, nullptr, nullptr);
 }
 
+// Chained step for many lattices: the k_fused_batch work table, 64x8 tiles, and each
+// instance's moments carried in mom[cur ^ parity] -> mom[cur ^ parity ^ 1].
+template <int NC>
+__global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3_batch(
+    const BatchInstance* __restrict__ inst, const WorkItem* __restrict__ work, int parity) {
+    __shared__ FusedTile<NC, 64, 8, true, true> L;
+    const int64_t bid = xcd_remap_f(blockIdx.x, gridDim.x);
+    const WorkItem w = work[bid];
+    const BatchInstance& bi = inst[w.inst];
+    const DevParams p = bi.p;
+    const int c = bi.cur ^ parity;
+    fused_tile<NC, 64, 8, true, true>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0, w.z0,
+                                      w.z1, bi.mom[c], bi.mom[c ^ 1]);
+}
+
 template <int NC, int TX, int TY>
 static hipError_t launch_fused_t(const DevParams& p, const Buffers& b, int zchunk, hipStream_t s) {
     const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
@@ -1187,6 +1202,17 @@ hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, i
         else
             hipLaunchKernelGGL((k_fused_batch<1, 32, 8>), grid, dim3(256), 0, s, inst, work, parity);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fused3_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int parity,
+                               hipStream_t s) {
+    if (nwork <= 0) return hipSuccess;
+    const dim3 grid((unsigned)nwork);
+    if (ncomp == 2)
+        hipLaunchKernelGGL((k_fused3_batch<2>), grid, dim3(1024), 0, s, inst, work, parity);
+    else
+        hipLaunchKernelGGL((k_fused3_batch<1>), grid, dim3(512), 0, s, inst, work, parity);
     return hipGetLastError();
 }
 

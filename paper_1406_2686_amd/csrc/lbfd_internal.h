@@ -62,6 +62,7 @@ struct BatchInstance {
     DevParams p;
     float* h[2];       // the two population buffers
     float* D[2];       // the two C - I buffers
+    float* mom[2];     // the two moments buffers (chained batch step; same parity as h and D)
     unsigned* flags;   // this instance's fault bits
     int cur;           // buffer index holding time level n when the launch parity is 0
     int pad;
@@ -86,6 +87,9 @@ hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, 
 hipError_t launch_fused3(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,
                               int parity, hipStream_t s);
+// chained step over a work table of 64x8 tiles (moments of level n in mom[cur ^ parity])
+hipError_t launch_fused3_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int parity,
+                               hipStream_t s);
 void fused_tile_shape(int ncomp, int tile, int* tx, int* ty);
 
 // field transfer kernels (k_fields.hip)

@@ -34,13 +34,17 @@ def small_cases():
     ]
 
 
-def singles(lb, cases, steps):
-    """Single-lattice references on the fused single-pass step, the tile body the batch
-    launch runs (the default two-pass step agrees with it to FP32 rounding only)."""
+def singles(lb, cases, steps, path=None):
+    """Single-lattice references on the tile body the batch launch runs: the fused
+    single-pass step by default (the default chained step agrees with it to FP32 rounding
+    only), or the chained step for a chained batch."""
     out = []
     for wl in cases:
         lat = lb.from_workload(wl)
-        lat.set_tuning(lb.PATH_FUSED)
+        if path is None or path == lb.PATH_FUSED:
+            lat.set_tuning(lb.PATH_FUSED)
+        else:
+            lat.set_tuning(path, "64x8", 0)
         lat.step(steps)
         out.append(lat.get_fields())
         lat.close()
@@ -52,6 +56,7 @@ def test_batch_matches_single_lattices_bitwise_over_graph_replays(lb):
     field reads run between the replays.  Every checkpoint is compared bitwise."""
     cases = small_cases()
     b = lb.Batch(cases)
+    b.set_tuning("32x8", 0, path=lb.PATH_FUSED)
     total = 0
     for n in (10, 7, 24, 1):
         b.step(n)
@@ -65,9 +70,39 @@ def test_batch_matches_single_lattices_bitwise_over_graph_replays(lb):
     b.close()
 
 
+def test_chained_batch_matches_chained_single_lattices_bitwise(lb):
+    """The chained body over the batch work table (64x8 tiles, each instance's moments
+    carried from step to step in its own buffers) against single lattices on the chained
+    step: bitwise over graph replays, odd step counts, diagnostics in between, a retired
+    instance (its moments wait with it) and its return."""
+    cases = small_cases()
+    b = lb.Batch(cases)
+    assert b.get_tuning()["path"] == lb.PATH_CHAINED  # the default
+    total = 0
+    for n in (10, 7, 1):
+        b.step(n)
+        total += n
+        b.diagnostics()
+        ref = singles(lb, cases, total, lb.PATH_CHAINED)
+        for i in range(len(cases)):
+            for a, r in zip(b.get_fields(i), ref[i]):
+                assert np.array_equal(a, r), (i, total)
+    b.set_active([True, False, True, True, True])
+    b.step(5)
+    b.set_active([True] * 5)
+    b.step(3)
+    ref = singles(lb, cases, total + 8, lb.PATH_CHAINED)
+    ref1 = singles(lb, [cases[1]], total + 3, lb.PATH_CHAINED)[0]
+    for i in range(len(cases)):
+        for a, r in zip(b.get_fields(i), ref1 if i == 1 else ref[i]):
+            assert np.array_equal(a, r), (i, "after retire")
+    b.close()
+
+
 def test_retired_instances_stay_frozen(lb):
     cases = small_cases()[:3]
     b = lb.Batch(cases)
+    b.set_tuning("32x8", 0, path=lb.PATH_FUSED)
     b.step(6)
     frozen = b.get_fields(1)
     b.set_active([True, False, True])
@@ -91,18 +126,26 @@ def test_retired_instances_stay_frozen(lb):
 def test_autotuners_pick_a_shape_and_leave_the_state_unchanged(lb):
     cases = small_cases()[:2]
     b = lb.Batch(cases)
+    b.set_tuning("32x8", 0, path=lb.PATH_FUSED)
     b.step(4)
     before = [b.get_fields(i) for i in range(2)]
     res = b.autotune(reps=2)
-    assert res["tile"] in ("32x8", "16x16") and res["zchunk"] >= 4 and res["ms_per_step"] > 0
+    assert res["tile"] in ("32x8", "16x16", "64x8") and res["zchunk"] >= 4 and res["ms_per_step"] > 0
+    assert (res["path"] == lb.PATH_CHAINED) == (res["tile"] == "64x8")
     for i in range(2):
         for a, r in zip(b.get_fields(i), before[i]):
             assert np.array_equal(a, r)
-    b.step(6)
-    ref = singles(lb, cases, 10)
+    b.step(6)  # on the shape the autotuner chose
     for i in range(2):
-        for a, r in zip(b.get_fields(i), ref[i]):
+        lat = lb.from_workload(cases[i])
+        lat.set_tuning(lb.PATH_FUSED)
+        lat.step(4)
+        if res["path"] == lb.PATH_CHAINED:
+            lat.set_tuning(lb.PATH_CHAINED, "64x8", 0)
+        lat.step(6)
+        for a, r in zip(b.get_fields(i), lat.get_fields()):
             assert np.array_equal(a, r)
+        lat.close()
     b.close()
     lat = lb.from_workload(cases[1])
     lat.step(3)
