@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "liblbfd_oracle.so")
 
 PHASE = {"none": 0, "A": 1, "B": 2, "all": 3}
 COUPLING = {"force": 0, "stress": 1}
+COLLISION = {"bgk": 0, "mrt": 1}
 FLAG_NONFINITE, FLAG_EXTENSIBILITY, FLAG_NOT_SPD = 1, 2, 4
 
 DIAG_FIELDS = (
@@ -75,6 +76,9 @@ def lib():
         L.orc_equilibrium_stress.argtypes = [ctypes.c_double, D, D, D]
         L.orc_source.argtypes = [D, D, D]
         L.orc_collide_node.argtypes = [D, ctypes.c_double, D, D, ctypes.c_double, D]
+        L.orc_collide_node_mrt.argtypes = [D, ctypes.c_double, D, D, ctypes.c_double, D]
+        L.orc_mrt_basis.argtypes = [D]
+        L.orc_set_collision.argtypes = [P, ctypes.c_int]
         L.orc_fenep_kinematic.argtypes = [P, D, ctypes.c_long]
         L.orc_fenep_kinematic.restype = ctypes.c_int
         L.orc_get_C.argtypes = [P, D]
@@ -133,13 +137,21 @@ def source(u, F) -> np.ndarray:
     return S
 
 
-def collide_node(f, rho, u, F, tau) -> np.ndarray:
+def collide_node(f, rho, u, F, tau, collision="bgk") -> np.ndarray:
     f = np.ascontiguousarray(f, dtype=np.float64)
     u = np.ascontiguousarray(u, dtype=np.float64)
     F = np.ascontiguousarray(F, dtype=np.float64)
     out = np.zeros(19)
-    lib().orc_collide_node(_dp(f), float(rho), _dp(u), _dp(F), float(tau), _dp(out))
+    fn = lib().orc_collide_node_mrt if collision == "mrt" else lib().orc_collide_node
+    fn(_dp(f), float(rho), _dp(u), _dp(F), float(tau), _dp(out))
     return out
+
+
+def mrt_basis() -> np.ndarray:
+    """The 19 x 19 moment basis of the MRT collision (rows: moments, columns: directions)."""
+    M = np.zeros(19 * 19)
+    lib().orc_mrt_basis(_dp(M))
+    return M.reshape(19, 19)
 
 
 class Oracle:
@@ -163,10 +175,11 @@ class Oracle:
             self._h = None
 
     def set_params(self, tau_A=1.0, tau_B=1.0, G=0.0, delta=0.1, polymer_phase="none",
-                   eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force"):
+                   eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force", collision="bgk"):
         ph = PHASE[polymer_phase] if isinstance(polymer_phase, str) else int(polymer_phase)
         cp = COUPLING[coupling] if isinstance(coupling, str) else int(coupling)
         lib().orc_set_params(self._h, tau_A, tau_B, G, delta, ph, eta_p, tau_p, L2, cp)
+        lib().orc_set_collision(self._h, COLLISION[collision] if isinstance(collision, str) else int(collision))
 
     def set_walls(self, u_bottom, u_top):
         ub = np.ascontiguousarray(u_bottom, dtype=np.float64)
@@ -231,7 +244,7 @@ def from_workload(wl) -> Oracle:
     p = wl["params"]
     o.set_params(tau_A=p["tau_A"], tau_B=p["tau_B"], G=p["G"], delta=p["delta"],
                  polymer_phase=p["polymer_phase"], eta_p=p["eta_p"], tau_p=p["tau_p"],
-                 L2=p["L2"], coupling=p.get("coupling", "force"))
+                 L2=p["L2"], coupling=p.get("coupling", "force"), collision=p.get("collision", "bgk"))
     o.set_walls(wl["walls"]["u_bottom"], wl["walls"]["u_top"])
     o.set_fields(wl["rho"], wl["u"], wl["C"])
     return o

@@ -23,7 +23,12 @@
  *       second moment of the equilibrium in S8 (eq. MODEtransformation)
  *   S6  velocity u = (j + sum_s F_s / 2)/rho                          (Sec. 2, eq. equilibrium:vel)
  *   S7  local BGK time tau = tau_B + (tau_A - tau_B) f+(phi)
- *   S8  BGK collision with the equilibrium and source of Sec. 2 (eq. LB with Lambda = I/tau)
+ *   S8  BGK collision with the equilibrium and source of Sec. 2 (eq. LB with Lambda = I/tau);
+ *       or, as an option, the multiple-relaxation-time collision of Sec. 2: moments
+ *       m = T f in an orthogonal D3Q19 basis, the bulk and shear modes relaxed with
+ *       1/tau (tau_s = tau_b = the local tau), the species momentum with 1/tau_M = 1 and
+ *       every other mode with rate 1 (eq. TRANSPORTCOEFF and the text after it), the
+ *       source weighted by (I - Lambda/2) in moment space
  *   S9  streaming; half-way bounce-back with the moving-wall correction at y walls
  *   S10 FENE-P: C += dt [ -(u.grad)_upwind C + G^T C + C G - (f C - I)/tau_P ],
  *       G_ij = d_i u_j (central), dt = 1                              (Sec. 2, eq. FENE)
@@ -76,12 +81,17 @@ static double W(int a) { return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 
 #define ORC_COUPLING_STRESS 1 /* T_s = (rho_s/rho) T subtracted from the equilibrium's second
                                  moment (Sec. 2, eq. MODEtransformation) */
 
+/* collision operator */
+#define ORC_COLLISION_BGK 0
+#define ORC_COLLISION_MRT 1
+
 typedef struct {
     int nx, ny, nz, nc;
     long N;
     double tauA, tauB, G, delta, eta_p, tau_p, L2;
     int phase;
     int coupling;
+    int collision;
     double ub[3], ut[3];
     double *f, *fn;   /* [nc][19][N] */
     double *C, *Cn;   /* [6][N]      */
@@ -147,6 +157,8 @@ void orc_set_params(orc_t *o, double tauA, double tauB, double G, double delta, 
     o->eta_p = eta_p; o->tau_p = tau_p; o->L2 = L2; o->coupling = coupling;
 }
 
+void orc_set_collision(orc_t *o, int collision) { o->collision = collision; }
+
 void orc_set_walls(orc_t *o, const double ub[3], const double ut[3]) {
     for (int d = 0; d < 3; d++) { o->ub[d] = ub[d]; o->ut[d] = ut[d]; }
 }
@@ -182,6 +194,89 @@ static double equilibrium_stress_term(int a, const double Ts[6]) {
                  2.0 * (c[0] * c[1] * Ts[3] + c[0] * c[2] * Ts[4] + c[1] * c[2] * Ts[5]);
     double tr = Ts[0] + Ts[1] + Ts[2];
     return -4.5 * W(a) * (cTc - tr / 3.0);
+}
+
+/* ------------------------------------------------------------------ MRT collision
+ *
+ * The paper names the moment basis of Premnath & Abraham (after d'Humieres et al.) without
+ * printing it.  Reading: the 19 moments below, polynomials in c_a that are mutually
+ * orthogonal over the 19 velocities (plain sum), in the usual order
+ *   0 rho   1 e   2 eps   3 j_x  4 q_x  5 j_y  6 q_y  7 j_z  8 q_z
+ *   9 3p_xx  10 3pi_xx  11 p_ww  12 pi_ww  13 p_xy  14 p_yz  15 p_xz  16 m_x  17 m_y  18 m_z.
+ * Rates: e and the five stresses (9, 11, 13, 14, 15) relax with 1/tau (the paper's
+ * tau_b = tau_s, space dependent through phi); the species momenta (3, 5, 7) with
+ * 1/tau_M = 1; the non-hydrodynamic modes with 1; rho is conserved.  The collision is
+ *   f* = f - T^-1 Lambda T (f - E) + T^-1 (I - Lambda/2) T S,
+ * with T^-1 = T^t diag(1/|m_i|^2) because the rows are orthogonal (a pin checks it). */
+static double mrt_row(int i, int a) {
+    double x = CX[a], y = CY[a], z = CZ[a];
+    double c2 = x * x + y * y + z * z;
+    switch (i) {
+        case 0: return 1.0;
+        case 1: return 19.0 * c2 - 30.0;
+        case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+        case 3: return x;
+        case 4: return (5.0 * c2 - 9.0) * x;
+        case 5: return y;
+        case 6: return (5.0 * c2 - 9.0) * y;
+        case 7: return z;
+        case 8: return (5.0 * c2 - 9.0) * z;
+        case 9: return 3.0 * x * x - c2;
+        case 10: return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+        case 11: return y * y - z * z;
+        case 12: return (3.0 * c2 - 5.0) * (y * y - z * z);
+        case 13: return x * y;
+        case 14: return y * z;
+        case 15: return x * z;
+        case 16: return (y * y - z * z) * x;
+        case 17: return (z * z - x * x) * y;
+        default: return (x * x - y * y) * z;
+    }
+}
+
+static double mrt_rate(int i, double tau) {
+    switch (i) {
+        case 1: case 9: case 11: case 13: case 14: case 15: return 1.0 / tau; /* bulk, shear */
+        default: return 1.0; /* rho (conserved), momenta (tau_M = 1), non-hydrodynamic */
+    }
+}
+
+/* f* at one node: f, E, S are the 19 populations, equilibrium and source. */
+static void mrt_collide(const double *f, const double *E, const double *S, double tau, double *out) {
+    double dm[NQ], sm[NQ], nrm[NQ];
+    for (int i = 0; i < NQ; i++) {
+        dm[i] = 0.0; sm[i] = 0.0; nrm[i] = 0.0;
+        for (int a = 0; a < NQ; a++) {
+            double m = mrt_row(i, a);
+            dm[i] += m * (f[a] - E[a]);
+            sm[i] += m * S[a];
+            nrm[i] += m * m;
+        }
+    }
+    for (int a = 0; a < NQ; a++) {
+        double v = f[a];
+        for (int i = 0; i < NQ; i++) {
+            double r = mrt_rate(i, tau);
+            v += mrt_row(i, a) / nrm[i] * (-r * dm[i] + (1.0 - 0.5 * r) * sm[i]);
+        }
+        out[a] = v;
+    }
+}
+
+void orc_mrt_basis(double *M) {
+    for (int i = 0; i < NQ; i++)
+        for (int a = 0; a < NQ; a++) M[i * NQ + a] = mrt_row(i, a);
+}
+
+/* One MRT collision of 19 populations at a single node (no streaming). */
+void orc_collide_node_mrt(const double *f, double rho, const double *u, const double *F, double tau,
+                          double *out) {
+    double E[NQ], S[NQ];
+    for (int a = 0; a < NQ; a++) {
+        E[a] = equilibrium(a, rho, u);
+        S[a] = source(a, u, F);
+    }
+    mrt_collide(f, E, S, tau, out);
 }
 
 static double fplus(const orc_t *o, double phi) { return 0.5 * (1.0 + tanh(phi / o->delta)); }
@@ -383,10 +478,21 @@ static void s8_s9_collide_stream(orc_t *o) {
                                    o->F[((long)s * 3 + 2) * N + n]};
                     double Ts[6];
                     for (int k = 0; k < 6; k++) Ts[k] = o->coupling == ORC_COUPLING_STRESS ? rs / rho * T[k] : 0.0;
+                    double fm[NQ], Em[NQ], Sm[NQ], pm[NQ];
+                    if (o->collision == ORC_COLLISION_MRT) {
+                        for (int a = 0; a < NQ; a++) {
+                            fm[a] = o->f[((long)s * NQ + a) * N + n];
+                            Em[a] = equilibrium(a, rs, u) + equilibrium_stress_term(a, Ts);
+                            Sm[a] = source(a, u, F);
+                        }
+                        mrt_collide(fm, Em, Sm, tau, pm);
+                    }
                     for (int a = 0; a < NQ; a++) {
                         double fa = o->f[((long)s * NQ + a) * N + n];
                         double Ea = equilibrium(a, rs, u) + equilibrium_stress_term(a, Ts);
-                        double post = fa - (fa - Ea) / tau + (1.0 - 0.5 / tau) * source(a, u, F);
+                        double post = o->collision == ORC_COLLISION_MRT
+                                          ? pm[a]
+                                          : fa - (fa - Ea) / tau + (1.0 - 0.5 / tau) * source(a, u, F);
                         int yd = y + CY[a];
                         if (yd >= 0 && yd < o->ny) {
                             long nd = IDX(o, wrap(x + CX[a], o->nx), yd, wrap(z + CZ[a], o->nz));
