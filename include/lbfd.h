@@ -79,7 +79,19 @@ typedef struct {
     double eta_p;          /* polymer viscosity (Sec. 2, eq. NS)                        */
     double tau_p;          /* polymer relaxation time in lattice steps (> 0)            */
     double L2;             /* FENE-P maximum extension squared (> 3)                    */
+    int32_t collision;     /* LBFD_COLLISION_*; any other value is EINVAL              */
+    int32_t reserved;      /* must be 0                                                 */
 } lbfd_params;
+
+/* Collision operator.  BGK: one relaxation time, the local tau (reading of the paper's
+ * collision at unit rates).  MRT: the multiple-relaxation-time collision of Sec. 2 in an
+ * orthogonal D3Q19 moment basis: the bulk and shear modes relax with the local tau
+ * (tau_s = tau_b), the species momenta with tau_M = 1, the other modes with rate 1, and
+ * the source is weighted by I - Lambda/2 in moment space (eq. TRANSPORTCOEFF and the text
+ * after it).  MRT runs on the three-pass split path (whatever lbfd_set_tuning selected;
+ * lbfd_get_tuning then reports LBFD_PATH_SPLIT); batches take BGK only. */
+#define LBFD_COLLISION_BGK 0
+#define LBFD_COLLISION_MRT 1
 
 /* FP64 diagnostics of the current state (droplet shape per Sec. 4.1: D = (a-b)/(a+b),
  * theta = angle of the major axis with the flow direction x, from the x-y block of the

@@ -157,7 +157,12 @@ void orc_set_params(orc_t *o, double tauA, double tauB, double G, double delta, 
     o->eta_p = eta_p; o->tau_p = tau_p; o->L2 = L2; o->coupling = coupling;
 }
 
-void orc_set_collision(orc_t *o, int collision) { o->collision = collision; }
+static void mrt_table(void);
+
+void orc_set_collision(orc_t *o, int collision) {
+    o->collision = collision;
+    if (collision == ORC_COLLISION_MRT) mrt_table(); /* before any parallel region reads it */
+}
 
 void orc_set_walls(orc_t *o, const double ub[3], const double ut[3]) {
     for (int d = 0; d < 3; d++) { o->ub[d] = ub[d]; o->ut[d] = ut[d]; }
@@ -241,29 +246,45 @@ static double mrt_rate(int i, double tau) {
     }
 }
 
+/* the basis as a table (filled once from mrt_row) and the squared row norms */
+static double MRT_M[NQ][NQ], MRT_N2[NQ];
+static void mrt_table(void) {
+    static int done = 0;
+    if (done) return;
+    for (int i = 0; i < NQ; i++) {
+        MRT_N2[i] = 0.0;
+        for (int a = 0; a < NQ; a++) {
+            MRT_M[i][a] = mrt_row(i, a);
+            MRT_N2[i] += MRT_M[i][a] * MRT_M[i][a];
+        }
+    }
+    done = 1;
+}
+
 /* f* at one node: f, E, S are the 19 populations, equilibrium and source. */
 static void mrt_collide(const double *f, const double *E, const double *S, double tau, double *out) {
-    double dm[NQ], sm[NQ], nrm[NQ];
+    double dm[NQ], sm[NQ];
     for (int i = 0; i < NQ; i++) {
-        dm[i] = 0.0; sm[i] = 0.0; nrm[i] = 0.0;
+        dm[i] = 0.0; sm[i] = 0.0;
         for (int a = 0; a < NQ; a++) {
-            double m = mrt_row(i, a);
-            dm[i] += m * (f[a] - E[a]);
-            sm[i] += m * S[a];
-            nrm[i] += m * m;
+            dm[i] += MRT_M[i][a] * (f[a] - E[a]);
+            sm[i] += MRT_M[i][a] * S[a];
         }
+    }
+    double corr[NQ];
+    for (int i = 0; i < NQ; i++) {
+        double r = mrt_rate(i, tau);
+        corr[i] = (-r * dm[i] + (1.0 - 0.5 * r) * sm[i]) / MRT_N2[i];
     }
     for (int a = 0; a < NQ; a++) {
         double v = f[a];
-        for (int i = 0; i < NQ; i++) {
-            double r = mrt_rate(i, tau);
-            v += mrt_row(i, a) / nrm[i] * (-r * dm[i] + (1.0 - 0.5 * r) * sm[i]);
-        }
+        for (int i = 0; i < NQ; i++) v += MRT_M[i][a] * corr[i];
         out[a] = v;
     }
 }
 
 void orc_mrt_basis(double *M) {
+    mrt_table();
     for (int i = 0; i < NQ; i++)
         for (int a = 0; a < NQ; a++) M[i * NQ + a] = mrt_row(i, a);
 }
@@ -276,6 +297,7 @@ void orc_collide_node_mrt(const double *f, double rho, const double *u, const do
         E[a] = equilibrium(a, rho, u);
         S[a] = source(a, u, F);
     }
+    mrt_table();
     mrt_collide(f, E, S, tau, out);
 }
 

@@ -29,6 +29,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENONFINITE"
 FLAG_NONFINITE, FLAG_EXTENSIBILITY, FLAG_NOT_SPD = 1, 2, 4
 POLYMER = {"none": 0, "A": 1, "B": 2, "all": 3}
 COUPLING = {"force": 0, "stress": 1}
+COLLISION = {"bgk": 0, "mrt": 1}
 
 
 class LbfdError(RuntimeError):
@@ -46,7 +47,8 @@ class Params(ctypes.Structure):
     _fields_ = [("tau_A", ctypes.c_double), ("tau_B", ctypes.c_double), ("G", ctypes.c_double),
                 ("delta", ctypes.c_double), ("rho0", ctypes.c_double * 2),
                 ("polymer_phase", ctypes.c_int32), ("coupling", ctypes.c_int32),
-                ("eta_p", ctypes.c_double), ("tau_p", ctypes.c_double), ("L2", ctypes.c_double)]
+                ("eta_p", ctypes.c_double), ("tau_p", ctypes.c_double), ("L2", ctypes.c_double),
+                ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):
@@ -171,12 +173,13 @@ def _dp(a):
 
 
 def make_params(tau_A=1.0, tau_B=1.0, G=0.0, delta=0.1, rho0=(1.0, 0.0), polymer_phase="none",
-                eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force", **_ignored) -> Params:
+                eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force", collision="bgk", **_ignored) -> Params:
     ph = POLYMER[polymer_phase] if isinstance(polymer_phase, str) else int(polymer_phase)
     cp = COUPLING[coupling] if isinstance(coupling, str) else int(coupling)
+    co = COLLISION[collision] if isinstance(collision, str) else int(collision)
     r0 = list(rho0) + [0.0] * (2 - len(rho0))
     return Params(float(tau_A), float(tau_B), float(G), float(delta),
-                  (ctypes.c_double * 2)(*r0), ph, cp, float(eta_p), float(tau_p), float(L2))
+                  (ctypes.c_double * 2)(*r0), ph, cp, float(eta_p), float(tau_p), float(L2), co, 0)
 
 
 def state_bytes(nx, ny, nz, ncomp) -> int:

@@ -260,22 +260,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
 #pragma unroll
         for (int k = 0; k < 6; ++k) Ts[k] = share * T[k];
         const float trs3 = (Ts[0] + Ts[1] + Ts[2]) * (1.0f / 3.0f);
-#pragma unroll
-        for (int a = 0; a < kQ; ++a) {
-            const float ha = hs[a * N + n];
-            const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
-            const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
-            float heq = wgt(a) * (drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
-            if (stress_eq) {
-                const float cTc = float(cx(a) * cx(a)) * Ts[0] + float(cy(a) * cy(a)) * Ts[1] +
-                                  float(cz(a) * cz(a)) * Ts[2] +
-                                  2.0f * (float(cx(a) * cy(a)) * Ts[3] + float(cx(a) * cz(a)) * Ts[4] +
-                                          float(cy(a) * cz(a)) * Ts[5]);
-                heq -= 4.5f * wgt(a) * (cTc - trs3);
-            }
-            const float src = wgt(a) * (3.0f * (cF - uFd) + 9.0f * cu * cF);
-            const float post = ha - om * (ha - heq) + cf * src;
-            check += post;
+        // push streaming of one post-collision population, bounce-back at the walls
+        auto emit = [&](int a, float post) {
             const int yd = y + cy(a);
             if (yd >= 0 && yd < ny) {
                 const int xd = cx(a) == 0 ? x : (cx(a) > 0 ? xp : xm);
@@ -283,8 +269,75 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
                 hns[a * N + ((int64_t)zd * ny + yd) * nx + xd] = post;
             } else {
                 const float* uw = yd < 0 ? p.ub : p.ut;
-                const float cuw = cx(a) * uw[0] + cz(a) * uw[2];
-                hns[opp(a) * N + n] = post - 6.0f * wgt(a) * rs * cuw;
+                hns[opp(a) * N + n] = post - 6.0f * wgt(a) * rs * wall_cu(a, uw);
+            }
+        };
+        // equilibrium (with the stress term of eq. MODEtransformation) and source of direction a
+        auto eq_src = [&](int a, float& heq, float& src) {
+            const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
+            const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
+            heq = wgt(a) * (drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+            if (stress_eq) {
+                const float cTc = float(cx(a) * cx(a)) * Ts[0] + float(cy(a) * cy(a)) * Ts[1] +
+                                  float(cz(a) * cz(a)) * Ts[2] +
+                                  2.0f * (float(cx(a) * cy(a)) * Ts[3] + float(cx(a) * cz(a)) * Ts[4] +
+                                          float(cy(a) * cz(a)) * Ts[5]);
+                heq -= 4.5f * wgt(a) * (cTc - trs3);
+            }
+            src = wgt(a) * (3.0f * (cF - uFd) + 9.0f * cu * cF);
+        };
+        if (p.collision == 1) {
+            // MRT (Sec. 2): with every rate 1 except the bulk and shear modes (rate om), the
+            // collision f - T^-1 Lambda T (f - E) + T^-1 (I - Lambda/2) T S reduces to
+            //   f* = E + S/2 + (1 - om) P2 (f - E + S/2),
+            // P2 the orthogonal projection on the modes e, 3p_xx, p_ww, p_xy, p_yz, p_xz of
+            // the D3Q19 basis (rows 19c^2 - 30, 3c_x^2 - c^2, c_y^2 - c_z^2, c_x c_y, c_y c_z,
+            // c_x c_z; squared norms 2394, 36, 12, 4, 4, 4)
+            float base[kQ];
+            float pe = 0.f, pxx = 0.f, pww = 0.f, pxy = 0.f, pyz = 0.f, pxz = 0.f;
+#pragma unroll
+            for (int a = 0; a < kQ; ++a) {
+                float heq, src;
+                eq_src(a, heq, src);
+                const float ha = hs[a * N + n];
+                const float g = ha - heq + 0.5f * src;
+                base[a] = heq + 0.5f * src;
+                const int c2 = cx(a) * cx(a) + cy(a) * cy(a) + cz(a) * cz(a);
+                pe += float(19 * c2 - 30) * g;
+                if (3 * cx(a) * cx(a) - c2 != 0) pxx += float(3 * cx(a) * cx(a) - c2) * g;
+                if (cy(a) * cy(a) - cz(a) * cz(a) != 0) pww += float(cy(a) * cy(a) - cz(a) * cz(a)) * g;
+                if (cx(a) * cy(a) != 0) pxy += float(cx(a) * cy(a)) * g;
+                if (cy(a) * cz(a) != 0) pyz += float(cy(a) * cz(a)) * g;
+                if (cx(a) * cz(a) != 0) pxz += float(cx(a) * cz(a)) * g;
+            }
+            const float k2 = 1.0f - om;
+            pe *= k2 * (1.0f / 2394.0f);
+            pxx *= k2 * (1.0f / 36.0f);
+            pww *= k2 * (1.0f / 12.0f);
+            pxy *= k2 * 0.25f;
+            pyz *= k2 * 0.25f;
+            pxz *= k2 * 0.25f;
+#pragma unroll
+            for (int a = 0; a < kQ; ++a) {
+                const int c2 = cx(a) * cx(a) + cy(a) * cy(a) + cz(a) * cz(a);
+                float post = base[a] + float(19 * c2 - 30) * pe;
+                if (3 * cx(a) * cx(a) - c2 != 0) post += float(3 * cx(a) * cx(a) - c2) * pxx;
+                if (cy(a) * cy(a) - cz(a) * cz(a) != 0) post += float(cy(a) * cy(a) - cz(a) * cz(a)) * pww;
+                if (cx(a) * cy(a) != 0) post += float(cx(a) * cy(a)) * pxy;
+                if (cy(a) * cz(a) != 0) post += float(cy(a) * cz(a)) * pyz;
+                if (cx(a) * cz(a) != 0) post += float(cx(a) * cz(a)) * pxz;
+                check += post;
+                emit(a, post);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < kQ; ++a) {
+                const float ha = hs[a * N + n];
+                float heq, src;
+                eq_src(a, heq, src);
+                const float post = ha - om * (ha - heq) + cf * src;
+                check += post;
+                emit(a, post);
             }
         }
     }

@@ -77,6 +77,8 @@ const char* params_problem(const lbfd_params* p) {
     if (p->eta_p < 0.0) return "eta_p must be non-negative";
     if (p->polymer_phase < LBFD_POLYMER_NONE || p->polymer_phase > LBFD_POLYMER_ALL) return "bad polymer_phase";
     if (p->coupling != LBFD_COUPLING_FORCE && p->coupling != LBFD_COUPLING_STRESS) return "bad coupling";
+    if (p->collision != LBFD_COLLISION_BGK && p->collision != LBFD_COLLISION_MRT) return "bad collision";
+    if (p->reserved != 0) return "reserved field must be 0";
     return nullptr;
 }
 
@@ -100,7 +102,7 @@ void fill_devparams(lbfd_ctx* c) {
     d.L2 = (float)p.L2;
     d.L2m3 = (float)(p.L2 - 3.0);
     d.coupling = p.coupling;
-    d.pad_ = 0;
+    d.collision = p.collision;
     for (int k = 0; k < 3; ++k) {
         d.ub[k] = (float)c->ub[k];
         d.ut[k] = (float)c->ut[k];
@@ -181,7 +183,7 @@ int auto_zchunk(const lbfd_grid& g, int tile) {
 hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
     for (int64_t t = 0; t < n; ++t) {
         hipError_t e;
-        if (c->tune.path == LBFD_PATH_SPLIT) {
+        if (c->tune.path == LBFD_PATH_SPLIT || c->dp.collision == LBFD_COLLISION_MRT) {
             e = launch_moments(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_forces(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_collide(c->dp, c->buf, c->stream);
@@ -203,7 +205,7 @@ hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
         }
         if (e != hipSuccess) return e;
         c->cur = 1 - c->cur;
-        if (c->tune.path == LBFD_PATH_CHAINED) {
+        if (c->tune.path == LBFD_PATH_CHAINED && c->dp.collision != LBFD_COLLISION_MRT) {
             c->mcur = 1 - c->mcur;  // the step wrote the moments of the new level
             c->mom_valid = true;
         } else {
@@ -581,8 +583,8 @@ lbfd_status lbfd_set_tuning(lbfd_ctx* c, const lbfd_tuning* t) {
 
 lbfd_status lbfd_get_tuning(lbfd_ctx* c, lbfd_tuning* t) {
     if (!c || !t) return LBFD_EINVAL;
-    t->path = c->tune.path;
-    t->tile = c->tune.path == LBFD_PATH_CHAINED ? LBFD_TILE_64x8 : c->tune.tile;
+    t->path = c->dp.collision == LBFD_COLLISION_MRT ? LBFD_PATH_SPLIT : c->tune.path;
+    t->tile = t->path == LBFD_PATH_CHAINED ? LBFD_TILE_64x8 : c->tune.tile;
     t->zchunk = c->tune.zchunk > 0 ? c->tune.zchunk : auto_zchunk(c->grid, t->tile);
     t->reserved = 0;
     return LBFD_OK;

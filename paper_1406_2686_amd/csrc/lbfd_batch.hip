@@ -309,8 +309,11 @@ lbfd_status lbfd_batch_set_active(lbfd_batch* b, const uint8_t* active) {
 
 lbfd_status lbfd_batch_step(lbfd_batch* b, int64_t nsteps) {
     if (!b || nsteps < 0) return LBFD_EINVAL;
-    for (int i = 0; i < b->n; ++i)
+    for (int i = 0; i < b->n; ++i) {
         if (b->active[i] && !b->inst[i]->have_fields) return bfail(b, LBFD_ESTATE, "instance without fields");
+        if (b->inst[i]->dp.collision != LBFD_COLLISION_BGK)
+            return bfail(b, LBFD_EINVAL, "batches take the BGK collision only");
+    }
     (void)hipSetDevice(b->device);
     BCHK(b, ensure_ready(b), "batch tables");
     BCHK(b, align_moments(b), "batch moments");

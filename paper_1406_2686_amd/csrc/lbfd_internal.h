@@ -21,7 +21,7 @@ struct DevParams {
     float L2m3;        // L^2 - 3
     float ub[3], ut[3];
     int coupling;      // LBFD_COUPLING_* (0: body force, 1: stress in the equilibrium)
-    int pad_;
+    int collision;     // LBFD_COLLISION_* (0: BGK, 1: MRT; the split path only)
 };
 
 // Views into the caller-owned device buffer.

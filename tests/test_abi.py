@@ -52,5 +52,36 @@ def test_structs_match_header_layout():
     import paper_1406_2686_amd as lb
 
     assert ctypes.sizeof(lb.Grid) == 16
-    assert ctypes.sizeof(lb.Params) == 8 * 6 + 8 + 8 * 3
+    assert ctypes.sizeof(lb.Params) == 8 * 6 + 8 + 8 * 3 + 8
     assert ctypes.sizeof(lb.Diag) == 8 * (2 + 3 + 1 + 3 + 6 + 5) + 8 + 8 + 8
+
+
+def test_struct_offsets_match_the_compiled_header(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset the C compiler gives it when
+    compiling include/lbfd.h (the header needs only <stdint.h>)."""
+    import shutil
+    import subprocess
+
+    import paper_1406_2686_amd as lb
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    pairs = [("lbfd_grid", lb.Grid), ("lbfd_params", lb.Params), ("lbfd_diag", lb.Diag),
+             ("lbfd_tuning", lb.Tuning), ("lbfd_steady_crit", lb.SteadyCrit), ("lbfd_train_opts", lb.TrainOpts)]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lbfd.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-I", inc, str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -418,6 +418,68 @@ def test_gpu_steady_shear_matches_lindner_closed_form(lb, Lam, coupling):
     assert np.allclose(u[0], -U + 2 * U * (Y + 0.5) / ny, atol=1e-4 * U)
 
 
+@pytest.mark.parametrize("case", ["droplet_visc_ratio", "couette_tau13", "droplet_stress_coupling"])
+def test_mrt_collision_matches_oracle(lb, case):
+    """The multiple-relaxation-time collision (Sec. 2; bulk and shear modes at the local
+    tau, species momenta at tau_M = 1, other modes at 1) on the split path against the
+    oracle's MRT: a droplet with viscosity ratio 0.4 (tau_A = 0.62, tau_B = 1.1, so tau
+    varies across the interface), the FENE-P Couette at tau = 1.3, and the stress coupling."""
+    if case == "droplet_visc_ratio":
+        wl = workloads.droplet_shear(nx=40, ny=24, nz=28, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                     polymer_phase="B", De=0.5, U=0.01, tau_A=0.62, tau_B=1.1)
+        steps = 400
+    elif case == "couette_tau13":
+        wl, steps = workloads.couette_fenep(nx=8, ny=32, nz=8, tau=1.3), 2000
+    else:
+        wl = workloads.droplet_shear(nx=37, ny=21, nz=29, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                     polymer_phase="A", De=1.0, U=0.01, tau_A=0.8, coupling="stress")
+        steps = 400
+    wl["params"]["collision"] = "mrt"
+    lat = lb.from_workload(wl)
+    assert lat.get_tuning()["path"] == lb.PATH_SPLIT  # MRT runs on the split path
+    lat.step(steps)
+    g = lat.get_fields()
+    dg = lat.diagnostics()
+    lat.close()
+    o = oracle.from_workload(wl)
+    assert o.step(steps) == 0
+    r = o.get_fields()
+    do = o.diagnostics()
+    e = report(f"mrt-{case}", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    for k in ("mass_A", "mass_B"):
+        assert abs(dg[k] - do[k]) <= 1e-6 * abs(do[k]) + 1e-9
+    if case != "couette_tau13":  # (a steady linear profile is the same under both)
+        # the two collisions differ here (tau != 1 at the droplet): MRT is not silently BGK
+        wl["params"]["collision"] = "bgk"
+        ob = oracle.from_workload(wl)
+        assert ob.step(steps) == 0
+        assert rel(ob.get_fields()[1], r[1]) > 100 * max(e["u"], 1e-7)
+
+
+def test_mrt_at_unit_tau_agrees_with_bgk_and_batches_refuse_it(lb):
+    """At tau = 1 every MRT rate is 1 and the step is the BGK step (FP32 rounding apart);
+    the batched bodies have no MRT and refuse it."""
+    wl = workloads.droplet_shear(nx=40, ny=20, nz=24, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="A", De=0.5, U=0.01)
+    out = []
+    for coll in ("mrt", "bgk"):
+        w = dict(wl, params=dict(wl["params"], collision=coll))
+        lat = lb.from_workload(w)
+        lat.set_tuning(lb.PATH_SPLIT)
+        lat.step(100)
+        out.append(lat.get_fields())
+        lat.close()
+    e = report("mrt-vs-bgk-tau1", out[0], out[1])
+    assert e["u"] < 2e-6 and e["rho"] < 1e-7 and e["C"] < 1e-7
+    w = dict(wl, params=dict(wl["params"], collision="mrt"))
+    b = lb.Batch([w])
+    with pytest.raises(lb.LbfdError) as ei:
+        b.step(2)
+    assert ei.value.status == lb.EINVAL
+    b.close()
+
+
 def test_full_size_droplet_sampled_window(lb):
     """The 1024x256x1024 droplet (268M nodes) in the launch configuration the benchmark
     times, checked against the oracle on a sampled window.  One step moves information at
