@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "liblbfd_oracle.so")
 PHASE = {"none": 0, "A": 1, "B": 2, "all": 3}
 COUPLING = {"force": 0, "stress": 1}
 COLLISION = {"bgk": 0, "mrt": 1}
+FENE = {"upwind_euler": 0, "cholesky_ab2": 1}
 FLAG_NONFINITE, FLAG_EXTENSIBILITY, FLAG_NOT_SPD = 1, 2, 4
 
 DIAG_FIELDS = (
@@ -79,6 +80,9 @@ def lib():
         L.orc_collide_node_mrt.argtypes = [D, ctypes.c_double, D, D, ctypes.c_double, D]
         L.orc_mrt_basis.argtypes = [D]
         L.orc_set_collision.argtypes = [P, ctypes.c_int]
+        L.orc_set_fene.argtypes = [P, ctypes.c_int, ctypes.c_double]
+        L.orc_cholesky_ab2.argtypes = [ctypes.c_double, D, D, D, ctypes.c_int, D, D,
+                                       ctypes.POINTER(ctypes.c_int)]
         L.orc_fenep_kinematic.argtypes = [P, D, ctypes.c_long]
         L.orc_fenep_kinematic.restype = ctypes.c_int
         L.orc_get_C.argtypes = [P, D]
@@ -147,6 +151,19 @@ def collide_node(f, rho, u, F, tau, collision="bgk") -> np.ndarray:
     return out
 
 
+def cholesky_ab2(L2, C, RC, yprev=None):
+    """One step of the Cholesky scheme at a node: C, dC/dt (6 each) and the previous rate of
+    (ln l11, l21, ln l22, l31, l32, ln l33) (None: forward Euler).  Returns (C_new, rate, flag)."""
+    C = np.ascontiguousarray(C, dtype=np.float64)
+    RC = np.ascontiguousarray(RC, dtype=np.float64)
+    yp = np.zeros(6) if yprev is None else np.ascontiguousarray(yprev, dtype=np.float64)
+    cn, yd = np.zeros(6), np.zeros(6)
+    flag = ctypes.c_int(0)
+    lib().orc_cholesky_ab2(float(L2), _dp(C), _dp(RC), _dp(yp), 0 if yprev is None else 1, _dp(cn), _dp(yd),
+                           ctypes.byref(flag))
+    return cn, yd, int(flag.value)
+
+
 def mrt_basis() -> np.ndarray:
     """The 19 x 19 moment basis of the MRT collision (rows: moments, columns: directions)."""
     M = np.zeros(19 * 19)
@@ -175,11 +192,13 @@ class Oracle:
             self._h = None
 
     def set_params(self, tau_A=1.0, tau_B=1.0, G=0.0, delta=0.1, polymer_phase="none",
-                   eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force", collision="bgk"):
+                   eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force", collision="bgk",
+                   fene="upwind_euler", kappa=0.0):
         ph = PHASE[polymer_phase] if isinstance(polymer_phase, str) else int(polymer_phase)
         cp = COUPLING[coupling] if isinstance(coupling, str) else int(coupling)
         lib().orc_set_params(self._h, tau_A, tau_B, G, delta, ph, eta_p, tau_p, L2, cp)
         lib().orc_set_collision(self._h, COLLISION[collision] if isinstance(collision, str) else int(collision))
+        lib().orc_set_fene(self._h, FENE[fene] if isinstance(fene, str) else int(fene), float(kappa))
 
     def set_walls(self, u_bottom, u_top):
         ub = np.ascontiguousarray(u_bottom, dtype=np.float64)
@@ -244,7 +263,8 @@ def from_workload(wl) -> Oracle:
     p = wl["params"]
     o.set_params(tau_A=p["tau_A"], tau_B=p["tau_B"], G=p["G"], delta=p["delta"],
                  polymer_phase=p["polymer_phase"], eta_p=p["eta_p"], tau_p=p["tau_p"],
-                 L2=p["L2"], coupling=p.get("coupling", "force"), collision=p.get("collision", "bgk"))
+                 L2=p["L2"], coupling=p.get("coupling", "force"), collision=p.get("collision", "bgk"),
+                 fene=p.get("fene", "upwind_euler"), kappa=p.get("kappa", 0.0))
     o.set_walls(wl["walls"]["u_bottom"], wl["walls"]["u_top"])
     o.set_fields(wl["rho"], wl["u"], wl["C"])
     return o

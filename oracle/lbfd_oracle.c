@@ -31,7 +31,11 @@
  *       source weighted by (I - Lambda/2) in moment space
  *   S9  streaming; half-way bounce-back with the moving-wall correction at y walls
  *   S10 FENE-P: C += dt [ -(u.grad)_upwind C + G^T C + C G - (f C - I)/tau_P ],
- *       G_ij = d_i u_j (central), dt = 1                              (Sec. 2, eq. FENE)
+ *       G_ij = d_i u_j (central), dt = 1                              (Sec. 2, eq. FENE);
+ *       or, as an option, the paper's integrator (Sec. 2, paragraph on the FENE-P solver):
+ *       sigma_P = f C = L L^t evolved through the Cholesky factor L with ln l_ii in place
+ *       of l_ii, second-order central differences in space, an artificial diffusivity
+ *       kappa lap C, and second-order Adams-Bashforth in time
  *   S11 fault checks (non-finite, tr C >= L^2, non-positive leading minor); never clips.
  *
  * Readings where the paper is silent (all listed in the design notes): BGK instead of
@@ -85,6 +89,10 @@ static double W(int a) { return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 
 #define ORC_COLLISION_BGK 0
 #define ORC_COLLISION_MRT 1
 
+/* FENE-P integrator */
+#define ORC_FENE_UPWIND_EULER 0
+#define ORC_FENE_CHOLESKY_AB2 1
+
 typedef struct {
     int nx, ny, nz, nc;
     long N;
@@ -92,6 +100,10 @@ typedef struct {
     int phase;
     int coupling;
     int collision;
+    int fene;         /* ORC_FENE_* */
+    double kappa;     /* artificial diffusivity of the Cholesky scheme */
+    double *Hp, *Hn;  /* [6][N] rate of (ln l11, l21, ln l22, l31, l32, ln l33) at the last step */
+    int have_hist;    /* Hp holds the previous rate (else the step is forward Euler) */
     double ub[3], ut[3];
     double *f, *fn;   /* [nc][19][N] */
     double *C, *Cn;   /* [6][N]      */
@@ -136,6 +148,8 @@ orc_t *orc_create(int nx, int ny, int nz, int nc) {
     o->F = (double *)calloc((size_t)nc * 3 * N, sizeof(double));
     o->u = (double *)calloc((size_t)3 * N, sizeof(double));
     o->tau = (double *)calloc((size_t)N, sizeof(double));
+    o->Hp = (double *)calloc((size_t)6 * N, sizeof(double));
+    o->Hn = (double *)calloc((size_t)6 * N, sizeof(double));
     o->tauA = o->tauB = 1.0;
     o->delta = 0.1;
     o->L2 = 100.0;
@@ -148,6 +162,7 @@ void orc_destroy(orc_t *o) {
     if (!o) return;
     free(o->f); free(o->fn); free(o->C); free(o->Cn); free(o->rho); free(o->j);
     free(o->phi); free(o->g); free(o->Fp); free(o->F); free(o->u); free(o->tau);
+    free(o->Hp); free(o->Hn);
     free(o);
 }
 
@@ -158,6 +173,12 @@ void orc_set_params(orc_t *o, double tauA, double tauB, double G, double delta, 
 }
 
 static void mrt_table(void);
+
+void orc_set_fene(orc_t *o, int scheme, double kappa) {
+    o->fene = scheme;
+    o->kappa = kappa;
+    o->have_hist = 0;
+}
 
 void orc_set_collision(orc_t *o, int collision) {
     o->collision = collision;
@@ -529,8 +550,97 @@ static void s8_s9_collide_stream(orc_t *o) {
             }
 }
 
+/* One step of the Cholesky scheme at one node.  C is the conformation tensor and RC its
+ * rate dC/dt (xx, yy, zz, xy, xz, yz order).  With sigma = f C and f = (L^2-3)/(L^2-tr C),
+ * f is also (L^2 - 3 + tr sigma)/L^2 and the rate of sigma is f RC + C f^2 tr(RC)/(L^2-3).
+ * For sigma = L L^t with L lower triangular, L' = L Phi(A), A = L^-1 sigma' L^-t, Phi(A) the
+ * strict lower part of A plus half its diagonal; so (ln l_ii)' = A_ii/2.  The variables
+ * y = (ln l11, l21, ln l22, l31, l32, ln l33) take one Adams-Bashforth-2 step with rate ydot
+ * and previous rate yprev (forward Euler when hist is 0).  Returns 0, or a fault flag when
+ * sigma is not positive definite or a value is not finite. */
+static int cholesky_ab2(double L2, const double c[6], const double RC[6], const double *yprev, int hist,
+                        double cnew[6], double ydot[6]) {
+    double Cm[3][3], Rm[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            Cm[a][b] = c[sym(a, b)];
+            Rm[a][b] = RC[sym(a, b)];
+        }
+    double trC = Cm[0][0] + Cm[1][1] + Cm[2][2], trR = Rm[0][0] + Rm[1][1] + Rm[2][2];
+    if (!(trC < L2)) return ORC_F_EXTENSIBILITY;
+    double f = (L2 - 3.0) / (L2 - trC);
+    double S[3][3], RS[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            S[a][b] = f * Cm[a][b];
+            RS[a][b] = f * Rm[a][b] + Cm[a][b] * f * f * trR / (L2 - 3.0);
+        }
+    /* Cholesky factor of sigma */
+    double Lm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j <= i; j++) {
+            double acc = S[i][j];
+            for (int k = 0; k < j; k++) acc -= Lm[i][k] * Lm[j][k];
+            if (i == j) {
+                if (!(acc > 0.0)) return ORC_F_NOT_SPD;
+                Lm[i][i] = sqrt(acc);
+            } else {
+                Lm[i][j] = acc / Lm[j][j];
+            }
+        }
+    /* A = L^-1 RS L^-t: X = L^-1 RS column by column, then A = (L^-1 X^t)^t */
+    double X[3][3], A[3][3];
+    for (int col = 0; col < 3; col++)
+        for (int i = 0; i < 3; i++) {
+            double acc = RS[i][col];
+            for (int k = 0; k < i; k++) acc -= Lm[i][k] * X[k][col];
+            X[i][col] = acc / Lm[i][i];
+        }
+    for (int col = 0; col < 3; col++)
+        for (int i = 0; i < 3; i++) {
+            double acc = X[col][i];
+            for (int k = 0; k < i; k++) acc -= Lm[i][k] * A[col][k];
+            A[col][i] = acc / Lm[i][i];
+        }
+    double Phi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j <= i; j++) Phi[i][j] = i == j ? 0.5 * A[i][i] : A[i][j];
+    double Ld[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            Ld[i][j] = 0.0;
+            for (int k = 0; k < 3; k++) Ld[i][j] += Lm[i][k] * Phi[k][j];
+        }
+    ydot[0] = 0.5 * A[0][0];
+    ydot[1] = Ld[1][0];
+    ydot[2] = 0.5 * A[1][1];
+    ydot[3] = Ld[2][0];
+    ydot[4] = Ld[2][1];
+    ydot[5] = 0.5 * A[2][2];
+    double y[6] = {log(Lm[0][0]), Lm[1][0], log(Lm[1][1]), Lm[2][0], Lm[2][1], log(Lm[2][2])};
+    for (int k = 0; k < 6; k++) y[k] += hist ? 1.5 * ydot[k] - 0.5 * yprev[k] : ydot[k];
+    double Ln[3][3] = {{exp(y[0]), 0, 0}, {y[1], exp(y[2]), 0}, {y[3], y[4], exp(y[5])}};
+    double Sn[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            Sn[a][b] = 0.0;
+            for (int k = 0; k < 3; k++) Sn[a][b] += Ln[a][k] * Ln[b][k];
+        }
+    double fn = (L2 - 3.0 + Sn[0][0] + Sn[1][1] + Sn[2][2]) / L2;
+    for (int a = 0; a < 3; a++)
+        for (int b = a; b < 3; b++) cnew[sym(a, b)] = Sn[a][b] / fn;
+    for (int k = 0; k < 6; k++)
+        if (!isfinite(cnew[k]) || !isfinite(ydot[k])) return ORC_F_NONFINITE;
+    return 0;
+}
+
+void orc_cholesky_ab2(double L2, const double *c, const double *RC, const double *yprev, int hist,
+                      double *cnew, double *ydot, int *flag) {
+    *flag = cholesky_ab2(L2, c, RC, yprev, hist, cnew, ydot);
+}
+
 /* S10: explicit Euler FENE-P update with upwind advection and central velocity
- * gradients, dt = 1 lattice step. */
+ * gradients, dt = 1 lattice step (or the Cholesky scheme, see cholesky_ab2). */
 static void s10_fenep(orc_t *o) {
     long N = o->N;
     int bad_all = 0;
@@ -555,9 +665,16 @@ static void s10_fenep(orc_t *o) {
                     u_at(o, xp, yp, zp, up);
                     u_at(o, xm, ym, zm, um);
                     for (int jd = 0; jd < 3; jd++) Gm[i][jd] = 0.5 * (up[jd] - um[jd]);
-                    /* first-order upwind difference along i */
                     double cn[6];
-                    if (u0[i] >= 0.0) {
+                    if (o->fene == ORC_FENE_CHOLESKY_AB2) {
+                        /* second-order central difference, and the artificial diffusivity */
+                        double cp[6];
+                        C_at(o, o->C, xp, yp, zp, cp);
+                        C_at(o, o->C, xm, ym, zm, cn);
+                        for (int k = 0; k < 6; k++)
+                            adv[k] += u0[i] * 0.5 * (cp[k] - cn[k]) - o->kappa * (cp[k] - 2.0 * c0[k] + cn[k]);
+                    } else if (u0[i] >= 0.0) {
+                        /* first-order upwind difference along i */
                         C_at(o, o->C, xm, ym, zm, cn);
                         for (int k = 0; k < 6; k++) adv[k] += u0[i] * (c0[k] - cn[k]);
                     } else {
@@ -569,14 +686,26 @@ static void s10_fenep(orc_t *o) {
                 double Cm[3][3];
                 for (int a = 0; a < 3; a++)
                     for (int b = 0; b < 3; b++) Cm[a][b] = c0[sym(a, b)];
+                double RC[6];
                 for (int a = 0; a < 3; a++)
                     for (int b = a; b < 3; b++) {
                         double stretch = 0;
                         for (int k = 0; k < 3; k++) stretch += Gm[k][a] * Cm[k][b] + Cm[a][k] * Gm[k][b];
                         int kk = sym(a, b);
                         double relax = (fr * c0[kk] - (a == b ? 1.0 : 0.0)) / o->tau_p;
-                        o->Cn[kk * N + n] = c0[kk] + (-adv[kk] + stretch - relax);
+                        RC[kk] = -adv[kk] + stretch - relax;
                     }
+                if (o->fene == ORC_FENE_CHOLESKY_AB2) {
+                    double yp6[6], cn6[6], yd6[6];
+                    for (int k = 0; k < 6; k++) yp6[k] = o->Hp[k * N + n];
+                    bad |= cholesky_ab2(o->L2, c0, RC, yp6, o->have_hist, cn6, yd6);
+                    for (int k = 0; k < 6; k++) {
+                        o->Cn[k * N + n] = cn6[k];
+                        o->Hn[k * N + n] = yd6[k];
+                    }
+                } else {
+                    for (int k = 0; k < 6; k++) o->Cn[k * N + n] = c0[k] + RC[k];
+                }
                 bad_all |= bad;
             }
     o->flags |= bad_all;
@@ -632,6 +761,7 @@ int orc_set_fields(orc_t *o, const double *rho, const double *u, const double *C
     memcpy(o->C, C, sizeof(double) * 6 * N);
     o->steps = 0;
     o->flags = 0;
+    o->have_hist = 0;
     return 0;
 }
 
@@ -646,6 +776,10 @@ int orc_step(orc_t *o, long nsteps) {
         s11_checks(o);
         double *tmp = o->f; o->f = o->fn; o->fn = tmp;
         tmp = o->C; o->C = o->Cn; o->Cn = tmp;
+        if (o->fene == ORC_FENE_CHOLESKY_AB2) {
+            tmp = o->Hp; o->Hp = o->Hn; o->Hn = tmp;
+            o->have_hist = 1;
+        }
         o->steps++;
         if (o->flags) return o->flags;
     }
@@ -790,6 +924,10 @@ int orc_fenep_kinematic(orc_t *o, const double *u, long nsteps) {
         o->flags = 0;
         s10_fenep(o);
         double *tmp = o->C; o->C = o->Cn; o->Cn = tmp;
+        if (o->fene == ORC_FENE_CHOLESKY_AB2) {
+            tmp = o->Hp; o->Hp = o->Hn; o->Hn = tmp;
+            o->have_hist = 1;
+        }
         if (o->flags) return o->flags;
     }
     return 0;
