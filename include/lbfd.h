@@ -80,8 +80,20 @@ typedef struct {
     double tau_p;          /* polymer relaxation time in lattice steps (> 0)            */
     double L2;             /* FENE-P maximum extension squared (> 3)                    */
     int32_t collision;     /* LBFD_COLLISION_*; any other value is EINVAL              */
-    int32_t reserved;      /* must be 0                                                 */
+    int32_t fene_scheme;   /* LBFD_FENE_*; any other value is EINVAL                    */
+    double fene_kappa;     /* artificial diffusivity of LBFD_FENE_CHOLESKY_AB2 (>= 0)    */
 } lbfd_params;
+
+/* FENE-P integrator.  UPWIND_EULER (default): C itself, first-order upwind advection,
+ * forward Euler (reading of the paper's integrator).  CHOLESKY_AB2: the paper's integrator
+ * (Sec. 2, paragraph on the FENE-P solver): sigma_P = f C = L L^t advanced through its
+ * Cholesky factor with ln l_ii in place of l_ii, so that C stays symmetric positive
+ * definite with tr C < L^2 by construction; second-order central differences in space,
+ * the artificial diffusivity fene_kappa * lap C, second-order Adams-Bashforth in time
+ * (forward Euler for the first step after set_fields).  Runs on the split path, like MRT;
+ * batches take UPWIND_EULER only. */
+#define LBFD_FENE_UPWIND_EULER 0
+#define LBFD_FENE_CHOLESKY_AB2 1
 
 /* Collision operator.  BGK: one relaxation time, the local tau (reading of the paper's
  * collision at unit rates).  MRT: the multiple-relaxation-time collision of Sec. 2 in an

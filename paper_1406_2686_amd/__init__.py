@@ -30,6 +30,7 @@ FLAG_NONFINITE, FLAG_EXTENSIBILITY, FLAG_NOT_SPD = 1, 2, 4
 POLYMER = {"none": 0, "A": 1, "B": 2, "all": 3}
 COUPLING = {"force": 0, "stress": 1}
 COLLISION = {"bgk": 0, "mrt": 1}
+FENE = {"upwind_euler": 0, "cholesky_ab2": 1}
 
 
 class LbfdError(RuntimeError):
@@ -48,7 +49,7 @@ class Params(ctypes.Structure):
                 ("delta", ctypes.c_double), ("rho0", ctypes.c_double * 2),
                 ("polymer_phase", ctypes.c_int32), ("coupling", ctypes.c_int32),
                 ("eta_p", ctypes.c_double), ("tau_p", ctypes.c_double), ("L2", ctypes.c_double),
-                ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("collision", ctypes.c_int32), ("fene_scheme", ctypes.c_int32), ("fene_kappa", ctypes.c_double)]
 
 
 class Diag(ctypes.Structure):
@@ -173,13 +174,16 @@ def _dp(a):
 
 
 def make_params(tau_A=1.0, tau_B=1.0, G=0.0, delta=0.1, rho0=(1.0, 0.0), polymer_phase="none",
-                eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force", collision="bgk", **_ignored) -> Params:
+                eta_p=0.0, tau_p=1000.0, L2=100.0, coupling="force", collision="bgk", fene="upwind_euler",
+                kappa=0.0, **_ignored) -> Params:
     ph = POLYMER[polymer_phase] if isinstance(polymer_phase, str) else int(polymer_phase)
     cp = COUPLING[coupling] if isinstance(coupling, str) else int(coupling)
     co = COLLISION[collision] if isinstance(collision, str) else int(collision)
+    fs = FENE[fene] if isinstance(fene, str) else int(fene)
     r0 = list(rho0) + [0.0] * (2 - len(rho0))
     return Params(float(tau_A), float(tau_B), float(G), float(delta),
-                  (ctypes.c_double * 2)(*r0), ph, cp, float(eta_p), float(tau_p), float(L2), co, 0)
+                  (ctypes.c_double * 2)(*r0), ph, cp, float(eta_p), float(tau_p), float(L2), co, fs,
+                  float(kappa))
 
 
 def state_bytes(nx, ny, nz, ncomp) -> int:

@@ -198,11 +198,86 @@ __global__ __launch_bounds__(kBlock) void k_forces(DevParams p, const float* __r
     if (bad) atomicOr(flags, bad);
 }
 
+// One step of the Cholesky scheme for the FENE-P equation (Sec. 2, paragraph on the FENE-P
+// solver) at one node.  c: C (xx, yy, zz, xy, xz, yz); rc: dC/dt.  sigma = f C with
+// f = (L^2 - 3)/(L^2 - tr C), so f = (L^2 - 3 + tr sigma)/L^2 and
+// sigma' = f rc + C f^2 tr(rc)/(L^2 - 3).  For sigma = L L^t (L lower triangular) the factor
+// moves as L' = L Phi(A), A = L^-1 sigma' L^-t, Phi = strict lower part + half the diagonal,
+// so (ln l_ii)' = A_ii / 2.  y = (ln l11, l21, ln l22, l31, l32, ln l33) takes one
+// Adams-Bashforth-2 step (forward Euler when hist is false); yd returns the rate.  The
+// new C is SPD with tr C < L^2 by construction.  Returns false if sigma is not SPD.
+__device__ bool cholesky_ab2_step(float L2, float L2m3, const float c[6], const float rc[6], const float yprev[6],
+                                  bool hist, float cn[6], float yd[6]) {
+    const float trc = c[0] + c[1] + c[2], trr = rc[0] + rc[1] + rc[2];
+    const float f = L2m3 / (L2 - trc);
+    const float g = f * f * trr / L2m3;
+    float s[6], r[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        s[k] = f * c[k];
+        r[k] = f * rc[k] + g * c[k];
+    }
+    // sigma = L L^t
+    const float a11 = s[0];
+    if (!(a11 > 0.0f)) return false;
+    const float l11 = sqrtf(a11);
+    const float l21 = s[3] / l11, l31 = s[4] / l11;
+    const float a22 = s[1] - l21 * l21;
+    if (!(a22 > 0.0f)) return false;
+    const float l22 = sqrtf(a22);
+    const float l32 = (s[5] - l31 * l21) / l22;
+    const float a33 = s[2] - l31 * l31 - l32 * l32;
+    if (!(a33 > 0.0f)) return false;
+    const float l33 = sqrtf(a33);
+    // X = L^-1 R (R symmetric 3x3 from r), then A = L^-1 X^t (A symmetric)
+    const float R[3][3] = {{r[0], r[3], r[4]}, {r[3], r[1], r[5]}, {r[4], r[5], r[2]}};
+    float X[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        X[0][j] = R[0][j] / l11;
+        X[1][j] = (R[1][j] - l21 * X[0][j]) / l22;
+        X[2][j] = (R[2][j] - l31 * X[0][j] - l32 * X[1][j]) / l33;
+    }
+    float A[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        A[j][0] = X[j][0] / l11;
+        A[j][1] = (X[j][1] - l21 * A[j][0]) / l22;
+        A[j][2] = (X[j][2] - l31 * A[j][0] - l32 * A[j][1]) / l33;
+    }
+    // L' = L Phi(A)
+    const float p11 = 0.5f * A[0][0], p22 = 0.5f * A[1][1], p33 = 0.5f * A[2][2];
+    const float p21 = A[1][0], p31 = A[2][0], p32 = A[2][1];
+    yd[0] = p11;
+    yd[1] = l21 * p11 + l22 * p21;
+    yd[2] = p22;
+    yd[3] = l31 * p11 + l32 * p21 + l33 * p31;
+    yd[4] = l32 * p22 + l33 * p32;
+    yd[5] = p33;
+    float y[6] = {logf(l11), l21, logf(l22), l31, l32, logf(l33)};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] += hist ? 1.5f * yd[k] - 0.5f * yprev[k] : yd[k];
+    const float m11 = expf(y[0]), m21 = y[1], m22 = expf(y[2]), m31 = y[3], m32 = y[4], m33 = expf(y[5]);
+    float sn[6];
+    sn[0] = m11 * m11;
+    sn[1] = m21 * m21 + m22 * m22;
+    sn[2] = m31 * m31 + m32 * m32 + m33 * m33;
+    sn[3] = m21 * m11;
+    sn[4] = m31 * m11;
+    sn[5] = m31 * m21 + m32 * m22;
+    const float fn = (L2m3 + sn[0] + sn[1] + sn[2]) / L2;
+    const float ifn = 1.0f / fn;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) cn[k] = sn[k] * ifn;
+    return true;
+}
+
 __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __restrict__ h,
                                                     float* __restrict__ hn,
                                                     const float* __restrict__ D,
                                                     float* __restrict__ Dn,
                                                     const float* __restrict__ uF,
+                                                    float* __restrict__ ab,
                                                     unsigned* __restrict__ flags) {
     const int64_t n = node_id();
     if (n >= p.N) return;
@@ -373,6 +448,18 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) Gm[i][d] = 0.5f * (up[d] - um[d]);
+        if (p.fene == 1) {
+            // second-order central difference and the artificial diffusivity (ghosts at
+            // the walls by linear extrapolation)
+            float dpl[6], dmi[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                dpl[k] = top ? 2.0f * d0[k] - D[k * N + n - nx] : D[k * N + mp];
+                dmi[k] = bot ? 2.0f * d0[k] - D[k * N + n + nx] : D[k * N + mm];
+                adv[k] += u[i] * (0.5f * (dpl[k] - dmi[k])) - p.kappa * (dpl[k] - 2.0f * d0[k] + dmi[k]);
+            }
+            continue;
+        }
         // first-order upwind difference of D along i
         float dn[6];
         if (u[i] >= 0.0f) {
@@ -404,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
     const float inv = 1.0f / den;
     const float f = p.L2m3 * inv;
     const float fm1 = trd * inv;
-    float dnew[6];
+    float dnew[6], rate[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -415,7 +502,27 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
 #pragma unroll
             for (int k = 0; k < 3; ++k) st += Gm[k][a] * d0[sidx(k, b)] + d0[sidx(a, k)] * Gm[k][b];
             const float relax = (f * d0[kk] + (a == b ? fm1 : 0.0f)) * p.inv_tau_p;
-            dnew[kk] = d0[kk] + (-adv[kk] + st - relax);
+            rate[kk] = -adv[kk] + st - relax;
+            dnew[kk] = d0[kk] + rate[kk];
+        }
+    }
+    if (p.fene == 1 && !(bad & 2u)) {
+        // the paper's integrator: the same rate, taken through the Cholesky factor of f C
+        float c6[6], rc[6], yp[6], cn[6], yd[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            c6[k] = (k < 3 ? 1.0f : 0.0f) + d0[k];
+            rc[k] = rate[k];
+            yp[k] = p.ab_hist ? ab[k * N + n] : 0.0f;
+        }
+        if (cholesky_ab2_step(p.L2, p.L2m3, c6, rc, yp, p.ab_hist != 0, cn, yd)) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                dnew[k] = cn[k] - (k < 3 ? 1.0f : 0.0f);
+                ab[k * N + n] = yd[k];
+            }
+        } else {
+            bad |= 4u;
         }
     }
 #pragma unroll
@@ -453,7 +560,7 @@ hipError_t launch_forces(const DevParams& p, const Buffers& b, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_collide(const DevParams& p, const Buffers& b, hipStream_t s) {
-    hipLaunchKernelGGL(k_collide, grid_for(p.N), dim3(kBlock), 0, s, p, b.h, b.hn, b.D, b.Dn, b.uF,
+    hipLaunchKernelGGL(k_collide, grid_for(p.N), dim3(kBlock), 0, s, p, b.h, b.hn, b.D, b.Dn, b.uF, b.ab,
                        b.flags);
     return hipGetLastError();
 }

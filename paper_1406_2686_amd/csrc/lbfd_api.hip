@@ -22,7 +22,7 @@ constexpr uint64_t kAlign = 256;
 inline uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t h0, h1, D0, D1, mom, mom2, uF, stage, red, red_out, flags, total;
+    uint64_t h0, h1, D0, D1, mom, mom2, uF, ab, stage, red, red_out, flags, total;
     int64_t stage_nodes, red_blocks;
 };
 
@@ -55,6 +55,7 @@ Layout layout(const lbfd_grid* g) {
     L.mom = take((uint64_t)(nc + 3) * N * 4);
     L.mom2 = take((uint64_t)(nc + 3) * N * 4);
     L.uF = take((uint64_t)(3 + 3 * nc) * N * 4);
+    L.ab = take((uint64_t)6 * N * 4);
     L.stage = take((uint64_t)11 * L.stage_nodes * 8);
     L.red = take((uint64_t)L.red_blocks * kDiagVals * 8);
     L.red_out = take((uint64_t)kDiagVals * 8);
@@ -78,7 +79,8 @@ const char* params_problem(const lbfd_params* p) {
     if (p->polymer_phase < LBFD_POLYMER_NONE || p->polymer_phase > LBFD_POLYMER_ALL) return "bad polymer_phase";
     if (p->coupling != LBFD_COUPLING_FORCE && p->coupling != LBFD_COUPLING_STRESS) return "bad coupling";
     if (p->collision != LBFD_COLLISION_BGK && p->collision != LBFD_COLLISION_MRT) return "bad collision";
-    if (p->reserved != 0) return "reserved field must be 0";
+    if (p->fene_scheme != LBFD_FENE_UPWIND_EULER && p->fene_scheme != LBFD_FENE_CHOLESKY_AB2) return "bad fene_scheme";
+    if (!is_fin(p->fene_kappa) || p->fene_kappa < 0.0) return "fene_kappa must be finite and >= 0";
     return nullptr;
 }
 
@@ -103,6 +105,10 @@ void fill_devparams(lbfd_ctx* c) {
     d.L2m3 = (float)(p.L2 - 3.0);
     d.coupling = p.coupling;
     d.collision = p.collision;
+    d.fene = p.fene_scheme;
+    d.kappa = (float)p.fene_kappa;
+    d.ab_hist = 0;
+    d.pad_ = 0;
     for (int k = 0; k < 3; ++k) {
         d.ub[k] = (float)c->ub[k];
         d.ut[k] = (float)c->ut[k];
@@ -183,7 +189,9 @@ int auto_zchunk(const lbfd_grid& g, int tile) {
 hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
     for (int64_t t = 0; t < n; ++t) {
         hipError_t e;
-        if (c->tune.path == LBFD_PATH_SPLIT || c->dp.collision == LBFD_COLLISION_MRT) {
+        if (c->tune.path == LBFD_PATH_SPLIT || c->dp.collision == LBFD_COLLISION_MRT ||
+            c->dp.fene == LBFD_FENE_CHOLESKY_AB2) {
+            c->dp.ab_hist = c->ab_valid ? 1 : 0;
             e = launch_moments(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_forces(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_collide(c->dp, c->buf, c->stream);
@@ -205,7 +213,9 @@ hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
         }
         if (e != hipSuccess) return e;
         c->cur = 1 - c->cur;
-        if (c->tune.path == LBFD_PATH_CHAINED && c->dp.collision != LBFD_COLLISION_MRT) {
+        c->ab_valid = c->dp.fene == LBFD_FENE_CHOLESKY_AB2;  // the split step wrote the rate
+        if (c->tune.path == LBFD_PATH_CHAINED && c->dp.collision != LBFD_COLLISION_MRT &&
+            c->dp.fene != LBFD_FENE_CHOLESKY_AB2) {
             c->mcur = 1 - c->mcur;  // the step wrote the moments of the new level
             c->mom_valid = true;
         } else {
@@ -299,6 +309,8 @@ lbfd_status lbfd_create(const lbfd_grid* grid, const lbfd_params* params, void* 
     c->mcur = 0;
     c->mom_valid = false;
     c->buf.uF = (float*)(c->dev + L.uF);
+    c->buf.ab = (float*)(c->dev + L.ab);
+    c->ab_valid = false;
     c->buf.stage = (double*)(c->dev + L.stage);
     c->buf.stage_nodes = L.stage_nodes;
     c->buf.red = (double*)(c->dev + L.red);
@@ -327,6 +339,7 @@ lbfd_status lbfd_create(const lbfd_grid* grid, const lbfd_params* params, void* 
 lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* params) {
     if (!c) return LBFD_EINVAL;
     if (const char* why = params_problem(params)) return fail(c, LBFD_EINVAL, why);
+    if (params->fene_scheme != c->params.fene_scheme) c->ab_valid = false;
     c->params = *params;
     fill_devparams(c);
     return LBFD_OK;
@@ -373,6 +386,7 @@ lbfd_status lbfd_set_fields_box(lbfd_ctx* c, int32_t x0, int32_t y0, int32_t z0,
     }
     c->have_fields = true;
     c->mom_valid = false;
+    c->ab_valid = false;
     return LBFD_OK;
 }
 
@@ -511,7 +525,7 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
 lbfd_status lbfd_checkpoint_bytes(lbfd_ctx* c, uint64_t* bytes) {
     if (!c || !bytes) return LBFD_EINVAL;
     const int64_t N = c->dp.N;
-    *bytes = 64 + (uint64_t)(c->grid.ncomp * 19 + 6 + c->grid.ncomp + 3) * N * 4;
+    *bytes = 64 + (uint64_t)(c->grid.ncomp * 19 + 6 + c->grid.ncomp + 3 + 6) * N * 4;
     return LBFD_OK;
 }
 
@@ -526,7 +540,7 @@ lbfd_status lbfd_get_state(lbfd_ctx* c, void* host, uint64_t bytes) {
     const int64_t N = c->dp.N;
     char* p = (char*)host;
     int64_t hdr[8] = {0x4c424644, (int64_t)c->grid.nx, (int64_t)c->grid.ny, (int64_t)c->grid.nz,
-                      (int64_t)c->grid.ncomp, c->steps, (int64_t)c->flags_seen, 0};
+                      (int64_t)c->grid.ncomp, c->steps, (int64_t)c->flags_seen, c->ab_valid ? 1 : 0};
     memcpy(p, hdr, 64);
     HIPCHK(c, hipMemcpyAsync(p + 64, c->buf.h, (size_t)c->grid.ncomp * 19 * N * 4, hipMemcpyDeviceToHost, c->stream),
            "state download");
@@ -537,6 +551,10 @@ lbfd_status lbfd_get_state(lbfd_ctx* c, void* host, uint64_t bytes) {
     HIPCHK(c, ensure_moments(c), "moments");
     HIPCHK(c, hipMemcpyAsync(p + 64 + (size_t)(c->grid.ncomp * 19 + 6) * N * 4, c->buf.mom,
                              (size_t)(c->grid.ncomp + 3) * N * 4, hipMemcpyDeviceToHost, c->stream),
+           "state download");
+    // the FENE-P integrator's history (second-order Adams-Bashforth)
+    HIPCHK(c, hipMemcpyAsync(p + 64 + (size_t)(c->grid.ncomp * 19 + 6 + c->grid.ncomp + 3) * N * 4, c->buf.ab,
+                             (size_t)6 * N * 4, hipMemcpyDeviceToHost, c->stream),
            "state download");
     HIPCHK(c, hipStreamSynchronize(c->stream), "state sync");
     return LBFD_OK;
@@ -561,7 +579,11 @@ lbfd_status lbfd_set_state(lbfd_ctx* c, const void* host, uint64_t bytes) {
     HIPCHK(c, hipMemcpyAsync(c->buf.mom, p + 64 + (size_t)(c->grid.ncomp * 19 + 6) * N * 4,
                              (size_t)(c->grid.ncomp + 3) * N * 4, hipMemcpyHostToDevice, c->stream),
            "state upload");
+    HIPCHK(c, hipMemcpyAsync(c->buf.ab, p + 64 + (size_t)(c->grid.ncomp * 19 + 6 + c->grid.ncomp + 3) * N * 4,
+                             (size_t)6 * N * 4, hipMemcpyHostToDevice, c->stream),
+           "state upload");
     c->mom_valid = true;
+    c->ab_valid = hdr[7] != 0;
     HIPCHK(c, launch_clear_flags(c->buf, c->stream), "clear flags");
     HIPCHK(c, hipStreamSynchronize(c->stream), "state sync");
     c->steps = hdr[5];
@@ -583,7 +605,8 @@ lbfd_status lbfd_set_tuning(lbfd_ctx* c, const lbfd_tuning* t) {
 
 lbfd_status lbfd_get_tuning(lbfd_ctx* c, lbfd_tuning* t) {
     if (!c || !t) return LBFD_EINVAL;
-    t->path = c->dp.collision == LBFD_COLLISION_MRT ? LBFD_PATH_SPLIT : c->tune.path;
+    t->path = (c->dp.collision == LBFD_COLLISION_MRT || c->dp.fene == LBFD_FENE_CHOLESKY_AB2) ? LBFD_PATH_SPLIT
+                                                                                               : c->tune.path;
     t->tile = t->path == LBFD_PATH_CHAINED ? LBFD_TILE_64x8 : c->tune.tile;
     t->zchunk = c->tune.zchunk > 0 ? c->tune.zchunk : auto_zchunk(c->grid, t->tile);
     t->reserved = 0;

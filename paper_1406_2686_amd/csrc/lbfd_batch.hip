@@ -311,8 +311,8 @@ lbfd_status lbfd_batch_step(lbfd_batch* b, int64_t nsteps) {
     if (!b || nsteps < 0) return LBFD_EINVAL;
     for (int i = 0; i < b->n; ++i) {
         if (b->active[i] && !b->inst[i]->have_fields) return bfail(b, LBFD_ESTATE, "instance without fields");
-        if (b->inst[i]->dp.collision != LBFD_COLLISION_BGK)
-            return bfail(b, LBFD_EINVAL, "batches take the BGK collision only");
+        if (b->inst[i]->dp.collision != LBFD_COLLISION_BGK || b->inst[i]->dp.fene != LBFD_FENE_UPWIND_EULER)
+            return bfail(b, LBFD_EINVAL, "batches take the BGK collision and the upwind-Euler FENE-P step only");
     }
     (void)hipSetDevice(b->device);
     BCHK(b, ensure_ready(b), "batch tables");

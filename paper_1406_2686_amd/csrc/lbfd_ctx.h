@@ -21,6 +21,7 @@ struct lbfd_ctx {
     int cur;
     int mcur;          // mbuf[mcur] holds the moments of the current level when mom_valid
     bool mom_valid;
+    bool ab_valid;     // buf.ab holds the FENE-P rate of the previous step (Cholesky AB2)
     hipStream_t stream;
     int device;
     char* dev;

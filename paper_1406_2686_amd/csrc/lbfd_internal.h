@@ -22,6 +22,10 @@ struct DevParams {
     float ub[3], ut[3];
     int coupling;      // LBFD_COUPLING_* (0: body force, 1: stress in the equilibrium)
     int collision;     // LBFD_COLLISION_* (0: BGK, 1: MRT; the split path only)
+    int fene;          // LBFD_FENE_* (0: upwind Euler, 1: Cholesky AB2; the split path only)
+    int ab_hist;       // Cholesky AB2: the history buffer holds the previous rate
+    float kappa;       // Cholesky AB2: artificial diffusivity
+    int pad_;
 };
 
 // Views into the caller-owned device buffer.
@@ -33,6 +37,7 @@ struct Buffers {
     float* mom;        // side field: [nc+3][N] = delta rho_A, (delta rho_B), j_x, j_y, j_z (level n)
     float* mom_next;   // the same at level n+1, written by the chained step
     float* uF;         // side field: [3+3nc][N] = u (half-force), F_A, (F_B)
+    float* ab;         // Cholesky AB2 history: [6][N] rate of (ln l11, l21, ln l22, l31, l32, ln l33)
     double* stage;     // FP64 staging for host transfers: 11 x stage_nodes
     int64_t stage_nodes;
     double* red;       // reduction partials

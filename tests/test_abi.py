@@ -52,7 +52,7 @@ def test_structs_match_header_layout():
     import paper_1406_2686_amd as lb
 
     assert ctypes.sizeof(lb.Grid) == 16
-    assert ctypes.sizeof(lb.Params) == 8 * 6 + 8 + 8 * 3 + 8
+    assert ctypes.sizeof(lb.Params) == 8 * 6 + 8 + 8 * 3 + 8 + 8
     assert ctypes.sizeof(lb.Diag) == 8 * (2 + 3 + 1 + 3 + 6 + 5) + 8 + 8 + 8
 
 

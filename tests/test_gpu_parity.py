@@ -480,6 +480,72 @@ def test_mrt_at_unit_tau_agrees_with_bgk_and_batches_refuse_it(lb):
     b.close()
 
 
+@pytest.mark.parametrize("case", ["couette", "droplet_kappa", "ragged_polyB"])
+def test_cholesky_ab2_fene_matches_oracle(lb, case):
+    """The paper's FENE-P integrator (Cholesky factor of f C with ln l_ii, central
+    differences, artificial diffusivity, Adams-Bashforth 2) on the split path against the
+    oracle: the FENE-P Couette, a droplet with kappa = 0.02, and a ragged droplet grid."""
+    if case == "couette":
+        wl, steps = workloads.couette_fenep(), 4000
+    elif case == "droplet_kappa":
+        wl = workloads.droplet_shear(nx=40, ny=24, nz=28, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                     polymer_phase="A", De=1.0, U=0.01)
+        wl["params"]["kappa"] = 0.02
+        steps = 600
+    else:
+        wl = workloads.droplet_shear(nx=37, ny=21, nz=29, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                     polymer_phase="B", De=0.5, U=0.008)
+        steps = 800
+    wl["params"]["fene"] = "cholesky_ab2"
+    lat = lb.from_workload(wl)
+    assert lat.get_tuning()["path"] == lb.PATH_SPLIT
+    lat.step(steps)
+    g = lat.get_fields()
+    assert lat.flags() == 0
+    lat.close()
+    o = oracle.from_workload(wl)
+    assert o.step(steps) == 0
+    r = o.get_fields()
+    e = report(f"cholesky-{case}", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
+
+
+def test_cholesky_ab2_steady_shear_and_restart(lb):
+    """GPU Cholesky scheme against the paper directly (steady shear at Lambda = 2.5,
+    L^2 = 100, eqs. lindner, lindner2), and a checkpoint split N + N that reproduces 2N
+    bitwise (the checkpoint carries the Adams-Bashforth history)."""
+    from paper_closed_forms import steady_shear_conformation
+
+    ny, tau_p, L2, Lam = 16, 200.0, 100.0, 2.5
+    U = Lam / tau_p * ny / 2.0
+    wl = workloads.couette_fenep(nx=2, ny=ny, nz=2, U=U, tau_p=tau_p, L2=L2, noise=0.0)
+    wl["params"]["eta_p"] = 1.0 / 24.0
+    wl["params"]["fene"] = "cholesky_ab2"
+    lat = lb.from_workload(wl)
+    lat.step(int(20 * tau_p))
+    C = lat.get_fields()[2]
+    lat.close()
+    ref = steady_shear_conformation(Lam, L2)
+    for k, key in enumerate(("xx", "yy", "zz", "xy")):
+        assert np.allclose(C[k], ref[key], rtol=5e-5, atol=5e-6), key
+    wl2 = workloads.droplet_shear(nx=40, ny=20, nz=24, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                  polymer_phase="A", De=1.0, U=0.01)
+    wl2["params"]["fene"] = "cholesky_ab2"
+    a = lb.from_workload(wl2)
+    a.step(150)
+    blob = a.get_state()
+    a.step(150)
+    b = lb.from_workload(wl2)
+    b.step(300)
+    c = lb.from_workload(wl2)
+    c.set_state(blob)
+    c.step(150)
+    for x, y, z in zip(a.get_fields(), b.get_fields(), c.get_fields()):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    for lat in (a, b, c):
+        lat.close()
+
+
 def test_full_size_droplet_sampled_window(lb):
     """The 1024x256x1024 droplet (268M nodes) in the launch configuration the benchmark
     times, checked against the oracle on a sampled window.  One step moves information at
