@@ -68,11 +68,12 @@ def recorded_traffic(workload, path_id):
     return rec
 
 
-def build_lattice(lb, workloads, nx, ny, nz, zchunk=16, collision="bgk"):
+def build_lattice(lb, workloads, nx, ny, nz, zchunk=16, collision="bgk", fene="upwind_euler"):
     """Create the droplet lattice and upload its fields slab by slab (host memory stays
     bounded for the 268M-node grid)."""
     wl0 = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(0, nx, 0, 1))
     wl0["params"]["collision"] = collision
+    wl0["params"]["fene"] = fene
     lat = lb.Lattice(nx, ny, nz, 2, wl0["params"])
     lat.set_walls(wl0["walls"]["u_bottom"], wl0["walls"]["u_top"])
     for z0 in range(0, nz, zchunk):
@@ -83,7 +84,7 @@ def build_lattice(lb, workloads, nx, ny, nz, zchunk=16, collision="bgk"):
     return lat, wl0
 
 
-def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk"):
+def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="upwind_euler"):
     """FP64 oracle on a 96 x ny x 96 sub-box window of the same workload (same per-node
     work), stepped until about `budget_s` seconds of CPU time have passed."""
     import oracle
@@ -94,6 +95,7 @@ def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk"):
     z0 = (nz - bz) // 2
     wl = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(x0, bx, z0, bz))
     wl["params"]["collision"] = collision
+    wl["params"]["fene"] = fene
     o = oracle.from_workload(wl)
     nodes = bx * ny * bz
     steps = 0
@@ -305,6 +307,8 @@ def main():
                     help="launch path of the step (default: the library's, the chained step)")
     ap.add_argument("--collision", choices=["bgk", "mrt"], default="bgk",
                     help="collision operator (MRT runs on the split path)")
+    ap.add_argument("--fene", choices=["upwind_euler", "cholesky_ab2"], default="upwind_euler",
+                    help="FENE-P integrator (the Cholesky scheme runs on the split path)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="droplet-sweep mode: plain vs batched vs surrogate (with solver fallback) time to steady D")
@@ -346,7 +350,7 @@ def main():
     N = nx * ny * nz
     torch.cuda.set_device(0)
     t_init = time.perf_counter()
-    lat, wl0 = build_lattice(lb, workloads, nx, ny, nz, collision=args.collision)
+    lat, wl0 = build_lattice(lb, workloads, nx, ny, nz, collision=args.collision, fene=args.fene)
     torch.cuda.synchronize()
     log(f"init {nx}x{ny}x{nz}: {time.perf_counter() - t_init:.1f} s")
 
@@ -401,7 +405,7 @@ def main():
         "config": {"workload": f"droplet_shear_{nx}x{ny}x{nz}", "nodes": N, "ncomp": 2,
                    "launch": {"path": ["fused", "split", "two-pass", "chained"][tuning["path"]], "tile": tuning["tile"],
                               "zchunk": tuning["zchunk"]},
-                   "collision": args.collision,
+                   "collision": args.collision, "fene": args.fene,
                    "droplet_R": wl0["meta"]["R"], "polymer": "matrix (L2=400, De=1)",
                    "diag_every": args.diag_every, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -417,7 +421,7 @@ def main():
     del lat
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(workloads, nx, ny, nz, collision=args.collision)
+        out["cpu_baseline"] = cpu_baseline(workloads, nx, ny, nz, collision=args.collision, fene=args.fene)
     print(json.dumps(out), flush=True)
 
 

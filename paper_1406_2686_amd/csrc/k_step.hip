@@ -217,33 +217,33 @@ __device__ bool cholesky_ab2_step(float L2, float L2m3, const float c[6], const 
         s[k] = f * c[k];
         r[k] = f * rc[k] + g * c[k];
     }
-    // sigma = L L^t
+    // sigma = L L^t; the triangular solves below multiply by the reciprocal diagonal
     const float a11 = s[0];
     if (!(a11 > 0.0f)) return false;
-    const float l11 = sqrtf(a11);
-    const float l21 = s[3] / l11, l31 = s[4] / l11;
+    const float l11 = sqrtf(a11), i11 = 1.0f / l11;
+    const float l21 = s[3] * i11, l31 = s[4] * i11;
     const float a22 = s[1] - l21 * l21;
     if (!(a22 > 0.0f)) return false;
-    const float l22 = sqrtf(a22);
-    const float l32 = (s[5] - l31 * l21) / l22;
+    const float l22 = sqrtf(a22), i22 = 1.0f / l22;
+    const float l32 = (s[5] - l31 * l21) * i22;
     const float a33 = s[2] - l31 * l31 - l32 * l32;
     if (!(a33 > 0.0f)) return false;
-    const float l33 = sqrtf(a33);
+    const float l33 = sqrtf(a33), i33 = 1.0f / l33;
     // X = L^-1 R (R symmetric 3x3 from r), then A = L^-1 X^t (A symmetric)
     const float R[3][3] = {{r[0], r[3], r[4]}, {r[3], r[1], r[5]}, {r[4], r[5], r[2]}};
     float X[3][3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        X[0][j] = R[0][j] / l11;
-        X[1][j] = (R[1][j] - l21 * X[0][j]) / l22;
-        X[2][j] = (R[2][j] - l31 * X[0][j] - l32 * X[1][j]) / l33;
+        X[0][j] = R[0][j] * i11;
+        X[1][j] = (R[1][j] - l21 * X[0][j]) * i22;
+        X[2][j] = (R[2][j] - l31 * X[0][j] - l32 * X[1][j]) * i33;
     }
     float A[3][3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        A[j][0] = X[j][0] / l11;
-        A[j][1] = (X[j][1] - l21 * A[j][0]) / l22;
-        A[j][2] = (X[j][2] - l31 * A[j][0] - l32 * A[j][1]) / l33;
+        A[j][0] = X[j][0] * i11;
+        A[j][1] = (X[j][1] - l21 * A[j][0]) * i22;
+        A[j][2] = (X[j][2] - l31 * A[j][0] - l32 * A[j][1]) * i33;
     }
     // L' = L Phi(A)
     const float p11 = 0.5f * A[0][0], p22 = 0.5f * A[1][1], p33 = 0.5f * A[2][2];
@@ -254,10 +254,12 @@ __device__ bool cholesky_ab2_step(float L2, float L2m3, const float c[6], const 
     yd[3] = l31 * p11 + l32 * p21 + l33 * p31;
     yd[4] = l32 * p22 + l33 * p32;
     yd[5] = p33;
-    float y[6] = {logf(l11), l21, logf(l22), l31, l32, logf(l33)};
+    // the diagonal moves as l_ii exp(step of ln l_ii): one exponential each, no logarithm
+    float st[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) y[k] += hist ? 1.5f * yd[k] - 0.5f * yprev[k] : yd[k];
-    const float m11 = expf(y[0]), m21 = y[1], m22 = expf(y[2]), m31 = y[3], m32 = y[4], m33 = expf(y[5]);
+    for (int k = 0; k < 6; ++k) st[k] = hist ? 1.5f * yd[k] - 0.5f * yprev[k] : yd[k];
+    const float m11 = l11 * __expf(st[0]), m21 = l21 + st[1], m22 = l22 * __expf(st[2]);
+    const float m31 = l31 + st[3], m32 = l32 + st[4], m33 = l33 * __expf(st[5]);
     float sn[6];
     sn[0] = m11 * m11;
     sn[1] = m21 * m21 + m22 * m22;
@@ -265,8 +267,7 @@ __device__ bool cholesky_ab2_step(float L2, float L2m3, const float c[6], const 
     sn[3] = m21 * m11;
     sn[4] = m31 * m11;
     sn[5] = m31 * m21 + m32 * m22;
-    const float fn = (L2m3 + sn[0] + sn[1] + sn[2]) / L2;
-    const float ifn = 1.0f / fn;
+    const float ifn = L2 / (L2m3 + sn[0] + sn[1] + sn[2]);
 #pragma unroll
     for (int k = 0; k < 6; ++k) cn[k] = sn[k] * ifn;
     return true;
