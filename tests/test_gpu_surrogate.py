@@ -4,7 +4,7 @@ A narrow droplet-in-shear family (only the capillary number varies) is solved to
 deformation by the batched solver; the network is trained on the device on those solves
 by the project's own kernels.  For held-out capillary numbers the network answers in a
 fraction of a millisecond what the solver needs a batched run to the steady test for, and
-its answers fall within |dD| <= 0.01 of the solver's steady D, the judge.  The warm start
+its answers fall within |dD| <= 0.01 of the solver's steady D, the reference.  The warm start
 built from its prediction keeps the droplet mass and leads the solver, used as fallback,
 to the same steady D."""
 import time
