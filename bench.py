@@ -24,6 +24,8 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per node and step (FP32): populations read + written
 # (2 x ncomp x 19 x 4) and C read + written (2 x 6 x 4)
 ALG_BYTES = {1: 200, 2: 352}
+# the Cholesky-log integrator also reads and writes its Adams-Bashforth history (2 x 6 x 4)
+ALG_BYTES_AB2_HISTORY = 48
 # kernels of one step per launch path (the chained step is the default)
 STEP_KERNELS = {0: "k_fused (one launch per step)", 1: "k_moments + k_forces + k_collide",
                 2: "k_moments + k_fused2 (two launches per step; bytes are the step's minimum)",
@@ -39,15 +41,16 @@ def log(*a):
 PROFILE_STEM = {2: "k_fused2", 3: "k_fused3"}
 
 
-def recorded_traffic(workload, path_id):
+def recorded_traffic(workload, path_id, default_options=True):
     """HBM bytes per step (the step's launches together) on `workload`, from the committed
     rocprofv3 counter summary of that launch path (FETCH_SIZE and WRITE_SIZE, each scaled
     by what the counter reads for a copy of known size).  Returned only while the kernel
     sources hash to the profiled ones; a changed kernel gives None until it is profiled
-    again."""
+    again.  The summaries profile the default options (BGK, upwind FENE-P): a run with
+    other options gets None."""
     import hashlib
 
-    if path_id not in PROFILE_STEM:
+    if path_id not in PROFILE_STEM or not default_options:
         return None
     path = os.path.join(ROOT, "profiles",
                         f"{PROFILE_STEM[path_id]}_{workload.replace('droplet_shear_', 'droplet_')}.md")
@@ -391,9 +394,11 @@ def main():
     log(f"timed {K} steps: wall {wall:.2f} s, {step_ms:.3f} ms/step (events), flags={flags}")
 
     mlups = N * K / wall / 1e6
-    alg = ALG_BYTES[2] * N
+    alg_node = ALG_BYTES[2] + (ALG_BYTES_AB2_HISTORY if args.fene == "cholesky_ab2" else 0)
+    alg = alg_node * N
     achieved = alg / (step_ms * 1e-3) / 1e9
-    rec = recorded_traffic(f"droplet_shear_{nx}x{ny}x{nz}", tuning["path"])
+    rec = recorded_traffic(f"droplet_shear_{nx}x{ny}x{nz}", tuning["path"],
+                           args.collision == "bgk" and args.fene == "upwind_euler")
     traffic = None if rec is None else round(rec["bytes_per_step"] / (step_ms * 1e-3) / 1e9, 1)
     mass_drift = max(abs(d1["mass_A"] - d0["mass_A"]) / d0["mass_A"],
                      abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"])
@@ -412,7 +417,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": STEP_KERNELS.get(tuning["path"], "?"),
                      "launches_per_step": LAUNCHES_PER_STEP[tuning["path"]],
-                     "alg_bytes_per_node": ALG_BYTES[2], "event_ms_per_step": round(step_ms, 4),
+                     "alg_bytes_per_node": alg_node, "event_ms_per_step": round(step_ms, 4),
                      "traffic_bytes_per_step": None if rec is None else rec["bytes_per_step"],
                      "traffic_source": None if rec is None else rec["path"]},
         "checks": {"fault_flags": flags, "mass_drift_rel": mass_drift, "D_final": d1["D"]},

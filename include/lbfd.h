@@ -90,8 +90,9 @@ typedef struct {
  * Cholesky factor with ln l_ii in place of l_ii, so that C stays symmetric positive
  * definite with tr C < L^2 by construction; second-order central differences in space,
  * the artificial diffusivity fene_kappa * lap C, second-order Adams-Bashforth in time
- * (forward Euler for the first step after set_fields).  Runs on the split path, like MRT;
- * batches take UPWIND_EULER only. */
+ * (forward Euler for the first step after set_fields).  Runs on the chained and split
+ * paths (a lattice tuned to the fused or two-pass path steps on the split path, and
+ * lbfd_get_tuning reports it); batches take UPWIND_EULER only. */
 #define LBFD_FENE_UPWIND_EULER 0
 #define LBFD_FENE_CHOLESKY_AB2 1
 
@@ -194,7 +195,9 @@ lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
  * of the current level are not at hand: after set_fields, another path or a batch; 64x8
  * tiles whatever `tile` says) or LBFD_PATH_SPLIT (three passes: moments, forces, collide;
  * kept as a cross-check).  The paths compute the same step; their results agree to FP32
- * rounding.  tile: LBFD_TILE_32x8 / 32x16 / 16x16 (x by y nodes per workgroup of the fused
+ * rounding.  A path that does not implement the lattice's collision or FENE-P option is
+ * replaced by the split path for the steps (see LBFD_COLLISION_MRT, LBFD_FENE_CHOLESKY_AB2);
+ * lbfd_get_tuning reports the path the steps take.  tile: LBFD_TILE_32x8 / 32x16 / 16x16 (x by y nodes per workgroup of the fused
  * and two-pass steps; 32x16 runs as 32x8).  zchunk: planes per workgroup along z, 0 =
  * automatic.  Within one path, results are identical for every tile and zchunk; only speed
  * changes. */
@@ -216,9 +219,10 @@ typedef struct {
 lbfd_status lbfd_set_tuning(lbfd_ctx* ctx, const lbfd_tuning* t);
 lbfd_status lbfd_get_tuning(lbfd_ctx* ctx, lbfd_tuning* t);
 
-/* Launch-shape autotuner (single lattice): times the chained, two-pass and fused steps for
- * every tile shape they take and a range of z-chunks on the current state, `reps` launches
- * each, and keeps the fastest
+/* Launch-shape autotuner (single lattice): times the chained, two-pass and fused steps that
+ * implement the lattice's options (the split step when none does) for every tile shape
+ * they take and a range of z-chunks on the current state, `reps` launches each, and keeps
+ * the fastest
  * (also returned in *best with its time in *ms_per_step; either may be NULL).  The trial
  * launches recompute the next time level from the current one without advancing, so the
  * lattice state, step counter and fault flags are unchanged.  ESTATE before set_fields. */

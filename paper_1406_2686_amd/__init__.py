@@ -308,8 +308,9 @@ class Lattice:
         return {"path": int(t.path), "tile": inv[int(t.tile)], "zchunk": int(t.zchunk)}
 
     def autotune(self, reps: int = 3) -> dict:
-        """Time every launch shape on the current state (which is left unchanged) and keep
-        the fastest; returns the chosen shape and its ms per step."""
+        """Time every launch shape that implements the lattice's options on the current
+        state (which is left unchanged) and keep the fastest; returns the chosen shape and
+        its ms per step."""
         t = Tuning()
         ms = ctypes.c_double(0)
         self._check(_lib.lbfd_autotune(self._h, int(reps), ctypes.byref(t), ctypes.byref(ms)))

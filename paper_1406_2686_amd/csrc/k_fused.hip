@@ -24,6 +24,7 @@
 // densities copy the wall layer, C is extrapolated linearly, u is reflected through the
 // wall velocity; x and z are periodic.
 #include "d3q19.h"
+#include "fene_chol.h"
 #include "lbfd_internal.h"
 
 namespace lbfd {
@@ -470,13 +471,19 @@ __device__ __forceinline__ void fold_dn(float v4, float v8, float v9, float v16,
 // What a thread receives in its own row goes into a ring of three partial moments in
 // registers (planes p-1, p, p+1 of the source plane p); what goes to the rows above and
 // below is folded to four values per row and passed on through LDS.
-template <int NC, int TX, int TY, bool TP, bool MO>
+// FE: 0 the upwind/Euler FENE-P update, 1 the Cholesky-log Adams-Bashforth-2 integrator with
+// central differences and artificial diffusivity (the rate of the previous step read from
+// `ab`, this step's written to `abn`, at the own node only).
+template <int NC, int TX, int TY, bool TP, bool MO, int FE = 0>
 __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __restrict__ h,
                                            float* __restrict__ hn, const float* __restrict__ D,
                                            float* __restrict__ Dn, unsigned* __restrict__ flags,
                                            FusedTile<NC, TX, TY, TP, MO>& L, int x0, int y0, int z0, int z1,
-                                           const float* __restrict__ mom, float* __restrict__ mom_out) {
+                                           const float* __restrict__ mom, float* __restrict__ mom_out,
+                                           const float* __restrict__ ab = nullptr,
+                                           float* __restrict__ abn = nullptr) {
     using T = FusedTile<NC, TX, TY, TP, MO>;
+    static_assert(FE == 0 || MO, "the Cholesky integrator runs in the chained body only");
     static_assert(!MO || (TP && TX == 64), "next-level moments: two-pass body, one tile row per wavefront");
     static_assert(T::NH2 <= T::NT, "one R2 halo node per thread at most");
     static_assert(T::A1 <= 2 * T::NTH, "phase B covers the R1 region in two passes at most");
@@ -718,6 +725,29 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                     }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) Gm[i][d] = 0.5f * (up[d] - um[d]);
+                    if constexpr (FE == 1) {
+                        // central difference and artificial diffusivity along i (the wall
+                        // ghosts in the rings are the linear extrapolations)
+                        float dpl[6], dmi[6];
+                        if (i == 2) {
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) {
+                                dpl[k] = L.cs[st1][k][oi2];
+                                dmi[k] = c_old[k];
+                            }
+                        } else {
+                            const int off = i == 0 ? 1 : T::W2;
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) {
+                                dpl[k] = L.cs[st][k][oi2 + off];
+                                dmi[k] = L.cs[st][k][oi2 - off];
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+                            adv[k] += u0[i] * (0.5f * (dpl[k] - dmi[k])) - p.kappa * (dpl[k] - 2.0f * d0[k] + dmi[k]);
+                        continue;
+                    }
                     float dn[6];
                     const bool bwd = u0[i] >= 0.0f;  // upwind: backward difference for u_i >= 0
                     if (i == 2) {
@@ -738,7 +768,7 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 const float inv = 1.0f / den;
                 const float f = p.L2m3 * inv;
                 const float fm1 = trd * inv;
-                float dnew[6];
+                float dnew[6], rate[6];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -748,10 +778,28 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
 #pragma unroll
                         for (int k = 0; k < 3; ++k) stv += Gm[k][a] * d0[sidx(k, b)] + d0[sidx(a, k)] * Gm[k][b];
                         const float relax = (f * d0[kk] + (a == b ? fm1 : 0.0f)) * p.inv_tau_p;
-                        dnew[kk] = d0[kk] + (-adv[kk] + stv - relax);
+                        rate[kk] = -adv[kk] + stv - relax;
+                        dnew[kk] = d0[kk] + rate[kk];
                     }
                 }
                 const uint32_t bt = ((uint32_t)t * plane + own_xy) * 4u;
+                if constexpr (FE == 1) {
+                    // the same rate taken through the Cholesky factor of f C, one AB2 step
+                    if (den > 0.0f) {
+                        float yp[6], dn6[6], yd[6];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) yp[k] = p.ab_hist ? ld_off(ab + (size_t)k * N, bt) : 0.0f;
+                        if (cholesky_ab2_step(p.L2, p.L2m3, d0, rate, yp, p.ab_hist != 0, dn6, yd)) {
+#pragma unroll
+                            for (int k = 0; k < 6; ++k) {
+                                dnew[k] = dn6[k];
+                                st_off(abn + (size_t)k * N, bt, yd[k]);
+                            }
+                        } else {
+                            bad |= 4u;
+                        }
+                    }
+                }
                 float check = 0.0f;
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
@@ -1091,11 +1139,13 @@ __global__ __launch_bounds__(NC* TX* TY, NC == 2 ? 4 : 2) void k_fused2(
 // Chained two-pass step: the second pass of step n, which also writes the moments of
 // level n+1 to `mom_out`, so that step n+1 starts from them without a moments pass.
 // 64x8 tiles only (one tile row per wavefront); 156 KB of LDS for two components.
-template <int NC>
+// FE selects the FENE-P integrator (0 upwind/Euler, 1 Cholesky-log AB2, its rate history
+// read from ab and written to abn).
+template <int NC, int FE>
 __global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3(
     DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
     float* __restrict__ Dn, const float* __restrict__ mom, float* __restrict__ mom_out, unsigned* __restrict__ flags,
-    int zchunk) {
+    int zchunk, const float* __restrict__ ab, float* __restrict__ abn) {
     constexpr int TX = 64, TY = 8;
     __shared__ FusedTile<NC, TX, TY, true, true> L;
     const int ntx = (p.nx + TX - 1) / TX, nty = (p.ny + TY - 1) / TY;
@@ -1104,8 +1154,8 @@ __global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3(
     int tx_i, ty_i, zc_i;
     tile_of_block(blockIdx.x, gridDim.x, ntx, nty, gxw, gyh, tx_i, ty_i, zc_i);
     const int z0 = zc_i * zchunk;
-    fused_tile<NC, TX, TY, true, true>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0,
-                                       min(z0 + zchunk, p.nz), mom, mom_out);
+    fused_tile<NC, TX, TY, true, true, FE>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0,
+                                           min(z0 + zchunk, p.nz), mom, mom_out, ab, abn);
 }
 
 // Many independent lattices in one launch: each workgroup takes one entry of the work
@@ -1172,19 +1222,20 @@ hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, 
     return launch_fused2_t<1, 32, 8>(p, b, zc, s);
 }
 
-template <int NC>
+template <int NC, int FE>
 static hipError_t launch_fused3_t(const DevParams& p, const Buffers& b, int zchunk, hipStream_t s) {
     const int ntx = (p.nx + 63) / 64, nty = (p.ny + 7) / 8;
     const int nzc = (p.nz + zchunk - 1) / zchunk;
     const int64_t nblk = (int64_t)ntx * nty * nzc;
-    hipLaunchKernelGGL((k_fused3<NC>), dim3((unsigned)nblk), dim3(NC * 64 * 8), 0, s, p, b.h, b.hn, b.D, b.Dn, b.mom,
-                       b.mom_next, b.flags, zchunk);
+    hipLaunchKernelGGL((k_fused3<NC, FE>), dim3((unsigned)nblk), dim3(NC * 64 * 8), 0, s, p, b.h, b.hn, b.D, b.Dn,
+                       b.mom, b.mom_next, b.flags, zchunk, b.ab, b.ab_next);
     return hipGetLastError();
 }
 
 hipError_t launch_fused3(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s) {
     const int zc = t.zchunk > 0 ? t.zchunk : p.nz;
-    return p.nc == 2 ? launch_fused3_t<2>(p, b, zc, s) : launch_fused3_t<1>(p, b, zc, s);
+    if (p.fene == 1) return p.nc == 2 ? launch_fused3_t<2, 1>(p, b, zc, s) : launch_fused3_t<1, 1>(p, b, zc, s);
+    return p.nc == 2 ? launch_fused3_t<2, 0>(p, b, zc, s) : launch_fused3_t<1, 0>(p, b, zc, s);
 }
 
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,

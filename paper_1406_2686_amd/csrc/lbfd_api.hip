@@ -22,7 +22,7 @@ constexpr uint64_t kAlign = 256;
 inline uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t h0, h1, D0, D1, mom, mom2, uF, ab, stage, red, red_out, flags, total;
+    uint64_t h0, h1, D0, D1, mom, mom2, uF, ab0, ab1, stage, red, red_out, flags, total;
     int64_t stage_nodes, red_blocks;
 };
 
@@ -55,7 +55,8 @@ Layout layout(const lbfd_grid* g) {
     L.mom = take((uint64_t)(nc + 3) * N * 4);
     L.mom2 = take((uint64_t)(nc + 3) * N * 4);
     L.uF = take((uint64_t)(3 + 3 * nc) * N * 4);
-    L.ab = take((uint64_t)6 * N * 4);
+    L.ab0 = take((uint64_t)6 * N * 4);
+    L.ab1 = take((uint64_t)6 * N * 4);
     L.stage = take((uint64_t)11 * L.stage_nodes * 8);
     L.red = take((uint64_t)L.red_blocks * kDiagVals * 8);
     L.red_out = take((uint64_t)kDiagVals * 8);
@@ -154,6 +155,8 @@ void bind_current(lbfd_ctx* c) {
     c->buf.Dn = c->Dbuf[1 - c->cur];
     c->buf.mom = c->mbuf[c->mcur];
     c->buf.mom_next = c->mbuf[1 - c->mcur];
+    c->buf.ab = c->abuf[c->cur];
+    c->buf.ab_next = c->abuf[1 - c->cur];
 }
 
 // moments of the current state in buf.mom: kept when they are already there (the chained
@@ -186,21 +189,32 @@ int auto_zchunk(const lbfd_grid& g, int tile) {
     return (int)std::min<int64_t>(zc, g.nz);
 }
 
+bool path_supports(const lbfd_ctx* c, int path) {
+    if (path == LBFD_PATH_SPLIT) return true;
+    // MRT collides each node from all 19 of its populations, which the tile bodies do not
+    // hold for their halo nodes; the Cholesky integrator is in the chained body only
+    if (c->dp.collision == LBFD_COLLISION_MRT) return false;
+    if (c->dp.fene == LBFD_FENE_CHOLESKY_AB2) return path == LBFD_PATH_CHAINED;
+    return true;
+}
+
+int step_path(const lbfd_ctx* c) { return path_supports(c, c->tune.path) ? c->tune.path : LBFD_PATH_SPLIT; }
+
 hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
+    const int path = step_path(c);
     for (int64_t t = 0; t < n; ++t) {
         hipError_t e;
-        if (c->tune.path == LBFD_PATH_SPLIT || c->dp.collision == LBFD_COLLISION_MRT ||
-            c->dp.fene == LBFD_FENE_CHOLESKY_AB2) {
-            c->dp.ab_hist = c->ab_valid ? 1 : 0;
+        c->dp.ab_hist = c->ab_valid ? 1 : 0;
+        if (path == LBFD_PATH_SPLIT) {
             e = launch_moments(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_forces(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_collide(c->dp, c->buf, c->stream);
-        } else if (c->tune.path == LBFD_PATH_TWOPASS) {
+        } else if (path == LBFD_PATH_TWOPASS) {
             Tuning tt = c->tune;
             if (tt.zchunk <= 0) tt.zchunk = auto_zchunk(c->grid, tt.tile);
             e = launch_moments(c->dp, c->buf, c->stream);
             if (e == hipSuccess) e = launch_fused2(c->dp, c->buf, tt, c->stream);
-        } else if (c->tune.path == LBFD_PATH_CHAINED) {
+        } else if (path == LBFD_PATH_CHAINED) {
             Tuning tt = c->tune;
             tt.tile = LBFD_TILE_64x8;
             if (tt.zchunk <= 0) tt.zchunk = auto_zchunk(c->grid, tt.tile);
@@ -213,9 +227,8 @@ hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
         }
         if (e != hipSuccess) return e;
         c->cur = 1 - c->cur;
-        c->ab_valid = c->dp.fene == LBFD_FENE_CHOLESKY_AB2;  // the split step wrote the rate
-        if (c->tune.path == LBFD_PATH_CHAINED && c->dp.collision != LBFD_COLLISION_MRT &&
-            c->dp.fene != LBFD_FENE_CHOLESKY_AB2) {
+        c->ab_valid = c->dp.fene == LBFD_FENE_CHOLESKY_AB2;  // the step wrote this step's rate
+        if (path == LBFD_PATH_CHAINED) {
             c->mcur = 1 - c->mcur;  // the step wrote the moments of the new level
             c->mom_valid = true;
         } else {
@@ -309,7 +322,8 @@ lbfd_status lbfd_create(const lbfd_grid* grid, const lbfd_params* params, void* 
     c->mcur = 0;
     c->mom_valid = false;
     c->buf.uF = (float*)(c->dev + L.uF);
-    c->buf.ab = (float*)(c->dev + L.ab);
+    c->abuf[0] = (float*)(c->dev + L.ab0);
+    c->abuf[1] = (float*)(c->dev + L.ab1);
     c->ab_valid = false;
     c->buf.stage = (double*)(c->dev + L.stage);
     c->buf.stage_nodes = L.stage_nodes;
@@ -605,8 +619,7 @@ lbfd_status lbfd_set_tuning(lbfd_ctx* c, const lbfd_tuning* t) {
 
 lbfd_status lbfd_get_tuning(lbfd_ctx* c, lbfd_tuning* t) {
     if (!c || !t) return LBFD_EINVAL;
-    t->path = (c->dp.collision == LBFD_COLLISION_MRT || c->dp.fene == LBFD_FENE_CHOLESKY_AB2) ? LBFD_PATH_SPLIT
-                                                                                               : c->tune.path;
+    t->path = step_path(c);
     t->tile = t->path == LBFD_PATH_CHAINED ? LBFD_TILE_64x8 : c->tune.tile;
     t->zchunk = c->tune.zchunk > 0 ? c->tune.zchunk : auto_zchunk(c->grid, t->tile);
     t->reserved = 0;

@@ -459,8 +459,10 @@ const char* lbfd_batch_last_error(const lbfd_batch* b) { return b ? b->err.c_str
 
 lbfd_ctx* lbfd_batch_instance(lbfd_batch* b, int32_t i) { return (b && i >= 0 && i < b->n) ? b->inst[i] : nullptr; }
 
-// Single-lattice autotuner: times the fused step for each tile shape and z-chunk on the
-// current state (trial launches do not advance it) and keeps the fastest.
+// Single-lattice autotuner: times each launch path that implements the lattice's options,
+// for each tile shape and z-chunk, on the current state (trial launches do not advance it)
+// and keeps the fastest.  A lattice whose options only the split path implements gets the
+// split path.
 lbfd_status lbfd_autotune(lbfd_ctx* c, int32_t reps, lbfd_tuning* best, double* ms_per_step) {
     if (!c || reps < 1) return LBFD_EINVAL;
     if (!c->have_fields) return LBFD_ESTATE;
@@ -471,12 +473,21 @@ lbfd_status lbfd_autotune(lbfd_ctx* c, int32_t reps, lbfd_tuning* best, double* 
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LBFD_EDEVICE;
     const int zcs[6] = {8, 16, 32, 64, 128, 256};
-    Tuning win = c->tune;
+    Tuning win{LBFD_PATH_SPLIT, c->tune.tile, c->tune.zchunk};
     float best_ms = 1e30f;
     // a trial step writes the other buffers (populations, C and moments of the next level)
-    // but does not swap, so the state is unchanged; the two-pass trials form their moments
-    // in the next level's moments buffer, so that moments carried by the chained step stay
+    // but does not swap, so the state is unchanged; the two-pass and split trials form their
+    // moments in the next level's moments buffer, so that moments carried by the chained
+    // step stay, and the FENE-P rate history goes to the next level's buffer as in a step
+    c->dp.ab_hist = c->ab_valid ? 1 : 0;
     auto trial = [&](const Tuning& t) -> hipError_t {
+        if (t.path == LBFD_PATH_SPLIT) {
+            Buffers tb = c->buf;
+            tb.mom = c->buf.mom_next;
+            hipError_t e = launch_moments(c->dp, tb, c->stream);
+            if (e == hipSuccess) e = launch_forces(c->dp, tb, c->stream);
+            return e != hipSuccess ? e : launch_collide(c->dp, tb, c->stream);
+        }
         if (t.path == LBFD_PATH_TWOPASS) {
             Buffers tb = c->buf;
             tb.mom = c->buf.mom_next;
@@ -489,28 +500,36 @@ lbfd_status lbfd_autotune(lbfd_ctx* c, int32_t reps, lbfd_tuning* best, double* 
         }
         return launch_fused(c->dp, c->buf, t, c->stream);
     };
-    for (int path : {LBFD_PATH_CHAINED, LBFD_PATH_TWOPASS, LBFD_PATH_FUSED})
-    for (int ti : {LBFD_TILE_32x8, LBFD_TILE_16x16, LBFD_TILE_64x8}) {
-        if (ti == LBFD_TILE_64x8 && path == LBFD_PATH_FUSED) continue;
-        if (ti != LBFD_TILE_64x8 && path == LBFD_PATH_CHAINED) continue;
-        for (int zc : zcs) {
-            if (zc > c->grid.nz && zc != 8) continue;
-            Tuning t{path, ti, std::min(zc, c->grid.nz)};
-            if (trial(t) != hipSuccess) return LBFD_EDEVICE;
-            (void)hipEventRecord(e0, c->stream);
-            for (int r = 0; r < reps; ++r)
-                if (trial(t) != hipSuccess) return LBFD_EDEVICE;
-            (void)hipEventRecord(e1, c->stream);
-            (void)hipEventSynchronize(e1);
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            ms /= reps;
-            if (ms < best_ms) {
-                best_ms = ms;
-                win = t;
+    auto time_it = [&](const Tuning& t) -> bool {
+        if (trial(t) != hipSuccess) return false;
+        (void)hipEventRecord(e0, c->stream);
+        for (int r = 0; r < reps; ++r)
+            if (trial(t) != hipSuccess) return false;
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_ms) {
+            best_ms = ms;
+            win = t;
+        }
+        return true;
+    };
+    bool any = false;
+    for (int path : {LBFD_PATH_CHAINED, LBFD_PATH_TWOPASS, LBFD_PATH_FUSED}) {
+        if (!path_supports(c, path)) continue;
+        for (int ti : {LBFD_TILE_32x8, LBFD_TILE_16x16, LBFD_TILE_64x8}) {
+            if (ti == LBFD_TILE_64x8 && path == LBFD_PATH_FUSED) continue;
+            if (ti != LBFD_TILE_64x8 && path == LBFD_PATH_CHAINED) continue;
+            for (int zc : zcs) {
+                if (zc > c->grid.nz && zc != 8) continue;
+                if (!time_it(Tuning{path, ti, std::min(zc, c->grid.nz)})) return LBFD_EDEVICE;
+                any = true;
             }
         }
     }
+    if (!any && !time_it(win)) return LBFD_EDEVICE;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     // the trials may have raised the same flags the next real step would; restore

@@ -18,6 +18,7 @@ struct lbfd_ctx {
     float* hbuf[2];
     float* Dbuf[2];
     float* mbuf[2];    // moments of two levels (the chained step reads one, writes the other)
+    float* abuf[2];    // FENE-P rate history, abuf[cur] read and abuf[1 - cur] written by a step
     int cur;
     int mcur;          // mbuf[mcur] holds the moments of the current level when mom_valid
     bool mom_valid;
@@ -37,6 +38,10 @@ hipError_t compute_side_fields(lbfd_ctx* c);
 hipError_t ensure_moments(lbfd_ctx* c);
 int auto_zchunk(const lbfd_grid& g, int tile);
 hipError_t enqueue_steps(lbfd_ctx* c, int64_t n);
+// whether a launch path implements the lattice's collision and FENE-P options, and the
+// path a step takes (the tuned one, or the split path when the tuned one lacks an option)
+bool path_supports(const lbfd_ctx* c, int path);
+int step_path(const lbfd_ctx* c);
 hipError_t read_flags(lbfd_ctx* c, unsigned* out);
 void bind_current(lbfd_ctx* c);
 }  // namespace lbfd

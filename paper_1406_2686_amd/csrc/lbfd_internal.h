@@ -37,7 +37,8 @@ struct Buffers {
     float* mom;        // side field: [nc+3][N] = delta rho_A, (delta rho_B), j_x, j_y, j_z (level n)
     float* mom_next;   // the same at level n+1, written by the chained step
     float* uF;         // side field: [3+3nc][N] = u (half-force), F_A, (F_B)
-    float* ab;         // Cholesky AB2 history: [6][N] rate of (ln l11, l21, ln l22, l31, l32, ln l33)
+    float* ab;         // Cholesky AB2 history: [6][N] rate of (ln l11, l21, ln l22, l31, l32, ln l33) at n-1
+    float* ab_next;    // the rate at n, written by the step (so a trial step leaves the state intact)
     double* stage;     // FP64 staging for host transfers: 11 x stage_nodes
     int64_t stage_nodes;
     double* red;       // reduction partials

@@ -480,11 +480,13 @@ def test_mrt_at_unit_tau_agrees_with_bgk_and_batches_refuse_it(lb):
     b.close()
 
 
+@pytest.mark.parametrize("path", ["chained", "split"])
 @pytest.mark.parametrize("case", ["couette", "droplet_kappa", "ragged_polyB"])
-def test_cholesky_ab2_fene_matches_oracle(lb, case):
+def test_cholesky_ab2_fene_matches_oracle(lb, case, path):
     """The paper's FENE-P integrator (Cholesky factor of f C with ln l_ii, central
-    differences, artificial diffusivity, Adams-Bashforth 2) on the split path against the
-    oracle: the FENE-P Couette, a droplet with kappa = 0.02, and a ragged droplet grid."""
+    differences, artificial diffusivity, Adams-Bashforth 2) against the oracle, in the
+    chained one-launch step (its default) and on the per-node split path: the FENE-P
+    Couette, a droplet with kappa = 0.02, and a ragged droplet grid."""
     if case == "couette":
         wl, steps = workloads.couette_fenep(), 4000
     elif case == "droplet_kappa":
@@ -498,7 +500,9 @@ def test_cholesky_ab2_fene_matches_oracle(lb, case):
         steps = 800
     wl["params"]["fene"] = "cholesky_ab2"
     lat = lb.from_workload(wl)
-    assert lat.get_tuning()["path"] == lb.PATH_SPLIT
+    if path == "split":
+        lat.set_tuning(lb.PATH_SPLIT)
+    assert lat.get_tuning()["path"] == (lb.PATH_SPLIT if path == "split" else lb.PATH_CHAINED)
     lat.step(steps)
     g = lat.get_fields()
     assert lat.flags() == 0
@@ -506,8 +510,66 @@ def test_cholesky_ab2_fene_matches_oracle(lb, case):
     o = oracle.from_workload(wl)
     assert o.step(steps) == 0
     r = o.get_fields()
-    e = report(f"cholesky-{case}", g, r)
+    e = report(f"cholesky-{case}-{path}", g, r)
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
+
+
+def test_mrt_with_cholesky_ab2_matches_oracle(lb):
+    """Both of the paper's options at once (MRT collision and the Cholesky-log integrator,
+    on the split path, the only one that has MRT) against the oracle with both."""
+    wl = workloads.droplet_shear(nx=36, ny=20, nz=26, R=5.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="A", De=1.0, U=0.01, tau_A=0.7, tau_B=1.2)
+    wl["params"]["collision"] = "mrt"
+    wl["params"]["fene"] = "cholesky_ab2"
+    wl["params"]["kappa"] = 0.01
+    lat = lb.from_workload(wl)
+    assert lat.get_tuning()["path"] == lb.PATH_SPLIT
+    lat.step(400)
+    g = lat.get_fields()
+    assert lat.flags() == 0
+    lat.close()
+    o = oracle.from_workload(wl)
+    assert o.step(400) == 0
+    e = report("mrt+cholesky", g, o.get_fields())
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
+
+
+def test_options_take_the_paths_that_implement_them(lb):
+    """A tuned path that lacks an option falls back to the split path (MRT: every tile path;
+    the Cholesky integrator: the single-pass and two-pass bodies).  The autotuner times only
+    paths that implement the options and leaves the state, the rate history included,
+    unchanged: a run that autotunes midway equals one that does not, bitwise."""
+    wl = workloads.droplet_shear(nx=40, ny=20, nz=24, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="A", De=1.0, U=0.01)
+    wc = dict(wl, params=dict(wl["params"], fene="cholesky_ab2"))
+    wm = dict(wl, params=dict(wl["params"], collision="mrt"))
+    lat = lb.from_workload(wc)
+    for path, want in ((lb.PATH_FUSED, lb.PATH_SPLIT), (lb.PATH_TWOPASS, lb.PATH_SPLIT),
+                       (lb.PATH_CHAINED, lb.PATH_CHAINED), (lb.PATH_SPLIT, lb.PATH_SPLIT)):
+        lat.set_tuning(path, "64x8" if path == lb.PATH_CHAINED else "32x8", 0)
+        assert lat.get_tuning()["path"] == want
+    lat.close()
+    for w, want in ((wc, lb.PATH_CHAINED), (wm, lb.PATH_SPLIT)):
+        a = lb.from_workload(w)
+        a.step(7)
+        before = a.get_fields()
+        t = a.autotune(reps=1)
+        assert t["path"] == want and a.get_tuning()["path"] == want
+        for x, y in zip(a.get_fields(), before):
+            assert np.array_equal(x, y)
+        a.step(9)
+        b = lb.from_workload(w)
+        if want == lb.PATH_CHAINED:
+            b.step(16)
+        else:
+            b.step(7)
+            b.set_tuning(lb.PATH_SPLIT)
+            b.step(9)
+        for x, y in zip(a.get_fields(), b.get_fields()):
+            assert np.array_equal(x, y)
+        assert a.flags() == 0
+        a.close()
+        b.close()
 
 
 def test_cholesky_ab2_steady_shear_and_restart(lb):
