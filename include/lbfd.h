@@ -101,8 +101,9 @@ typedef struct {
  * orthogonal D3Q19 moment basis: the bulk and shear modes relax with the local tau
  * (tau_s = tau_b), the species momenta with tau_M = 1, the other modes with rate 1, and
  * the source is weighted by I - Lambda/2 in moment space (eq. TRANSPORTCOEFF and the text
- * after it).  MRT runs on the three-pass split path (whatever lbfd_set_tuning selected;
- * lbfd_get_tuning then reports LBFD_PATH_SPLIT); batches take BGK only. */
+ * after it).  MRT runs on the chained and split paths (a lattice tuned to the fused or
+ * two-pass path steps on the split path, and lbfd_get_tuning reports it); batches take BGK
+ * only. */
 #define LBFD_COLLISION_BGK 0
 #define LBFD_COLLISION_MRT 1
 

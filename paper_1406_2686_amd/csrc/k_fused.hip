@@ -421,6 +421,93 @@ __device__ __forceinline__ void collide_pair(const CollideIn& c, int a, float ha
     collide_pair_c(c, float(cx(a)), float(cy(a)), float(cz(a)), wgt(a), ha, hb, pa, pb);
 }
 
+// MRT collision (Sec. 2) with every rate 1 except the bulk and shear modes (rate 1/tau):
+//   f* = E + S/2 + (1 - 1/tau) P2 (f - E + S/2),
+// P2 the orthogonal projection on the modes e, 3p_xx, p_ww, p_xy, p_yz, p_xz of the D3Q19
+// basis (rows 19c^2 - 30, 3c_x^2 - c^2, c_y^2 - c_z^2, c_x c_y, c_y c_z, c_x c_z; squared
+// norms 2394, 36, 12, 4, 4, 4).  Mrt holds (1 - 1/tau) times the six projection
+// coefficients of a node; every node is collided from all 19 of its populations, whichever
+// tile does it, with the same fixed fma pattern (contraction off), so the values a halo
+// collide forms are those of the node's own tile, bit for bit.
+struct Mrt {
+    float e, xx, ww, xy, yz, xz;
+};
+
+// E and S of direction (ex, ey, ez) with weight w (the stress term of eq. MODEtransformation
+// in E when the stress coupling is on)
+__device__ __forceinline__ void mrt_eq_src(const CollideIn& c, float ex, float ey, float ez, float w, float& E,
+                                           float& S) {
+#pragma clang fp contract(off)
+    const float cu = fmaf(ez, c.u[2], fmaf(ey, c.u[1], ex * c.u[0]));
+    const float cF = fmaf(ez, c.F[2], fmaf(ey, c.F[1], ex * c.F[0]));
+    float ee = w * fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs);
+    if (c.stress) {
+        const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
+                          2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
+        ee = fmaf(-4.5f * w, cTc - c.trs3, ee);
+    }
+    E = ee + ((3.0f * w) * c.rs) * cu;
+    S = w * fmaf(9.0f * cu, cF, -3.0f * c.uF) + (3.0f * w) * cF;
+}
+
+// the projection coefficients of a node from its 19 populations h.  The coefficients are
+// moments of g = f - E + S/2 of order two and below, and the lattice's fourth-order
+// isotropy gives those of E and S in closed form:
+//   sum E = delta rho_s, sum E c_i c_j = delta rho_s / 3 d_ij + rho_s u_i u_j - T_s,ij,
+//   sum S = 0,           sum S c_i c_j = u_i F_j + u_j F_i,
+// so only the populations' own moments are summed.
+__device__ __forceinline__ Mrt mrt_coef(const CollideIn& c, const float (&h)[kQ]) {
+#pragma clang fp contract(off)
+    float s0 = 0.f, sxx = 0.f, syy = 0.f, szz = 0.f, sxy = 0.f, syz = 0.f, sxz = 0.f;
+#pragma unroll
+    for (int a = 0; a < kQ; ++a) {
+        s0 += h[a];
+        if (cx(a) != 0) sxx += h[a];
+        if (cy(a) != 0) syy += h[a];
+        if (cz(a) != 0) szz += h[a];
+        if (cx(a) * cy(a) > 0) sxy += h[a];
+        if (cx(a) * cy(a) < 0) sxy -= h[a];
+        if (cy(a) * cz(a) > 0) syz += h[a];
+        if (cy(a) * cz(a) < 0) syz -= h[a];
+        if (cx(a) * cz(a) > 0) sxz += h[a];
+        if (cx(a) * cz(a) < 0) sxz -= h[a];
+    }
+    const float d3 = c.drs * (1.0f / 3.0f);
+    const float* u = c.u;
+    const float* F = c.F;
+    const float gxx = (sxx - (fmaf(c.rs * u[0], u[0], d3) - c.Ts[0])) + u[0] * F[0];
+    const float gyy = (syy - (fmaf(c.rs * u[1], u[1], d3) - c.Ts[1])) + u[1] * F[1];
+    const float gzz = (szz - (fmaf(c.rs * u[2], u[2], d3) - c.Ts[2])) + u[2] * F[2];
+    const float gxy = (sxy - (c.rs * u[0] * u[1] - c.Ts[3])) + 0.5f * fmaf(u[0], F[1], u[1] * F[0]);
+    const float gxz = (sxz - (c.rs * u[0] * u[2] - c.Ts[4])) + 0.5f * fmaf(u[0], F[2], u[2] * F[0]);
+    const float gyz = (syz - (c.rs * u[1] * u[2] - c.Ts[5])) + 0.5f * fmaf(u[1], F[2], u[2] * F[1]);
+    const float g0 = s0 - c.drs;
+    const float tr = (gxx + gyy) + gzz;
+    const float k2 = 1.0f - c.om;
+    return Mrt{fmaf(19.0f, tr, -30.0f * g0) * (k2 * (1.0f / 2394.0f)), fmaf(2.0f, gxx, -(gyy + gzz)) * (k2 * (1.0f / 36.0f)),
+               (gyy - gzz) * (k2 * (1.0f / 12.0f)), gxy * (k2 * 0.25f), gyz * (k2 * 0.25f), gxz * (k2 * 0.25f)};
+}
+
+// post-collision population of direction (ex, ey, ez) (a run-time or compile-time value:
+// the rows are exact small integers either way)
+__device__ __forceinline__ float mrt_post_c(const CollideIn& c, const Mrt& m, float ex, float ey, float ez, float w) {
+#pragma clang fp contract(off)
+    float E, S;
+    mrt_eq_src(c, ex, ey, ez, w, E, S);
+    const float c2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+    float post = fmaf(0.5f, S, E);
+    post = fmaf(fmaf(19.0f, c2, -30.0f), m.e, post);
+    post = fmaf(fmaf(3.0f * ex, ex, -c2), m.xx, post);
+    post = fmaf(fmaf(ey, ey, -(ez * ez)), m.ww, post);
+    post = fmaf(ex * ey, m.xy, post);
+    post = fmaf(ey * ez, m.yz, post);
+    post = fmaf(ex * ez, m.xz, post);
+    return post;
+}
+__device__ __forceinline__ float mrt_post(const CollideIn& c, const Mrt& m, int a) {
+    return mrt_post_c(c, m, float(cx(a)), float(cy(a)), float(cz(a)), wgt(a));
+}
+
 // the pairs with c_x != 0 (their odd member has c_x = +1): 1, 7, 9, 11, 13
 __host__ __device__ constexpr int xpair(int m) { return m == 0 ? 1 : 5 + 2 * m; }
 __host__ __device__ constexpr int xpair_index(int a) { return a == 1 ? 0 : (a - 5) / 2; }
@@ -474,7 +561,7 @@ __device__ __forceinline__ void fold_dn(float v4, float v8, float v9, float v16,
 // FE: 0 the upwind/Euler FENE-P update, 1 the Cholesky-log Adams-Bashforth-2 integrator with
 // central differences and artificial diffusivity (the rate of the previous step read from
 // `ab`, this step's written to `abn`, at the own node only).
-template <int NC, int TX, int TY, bool TP, bool MO, int FE = 0>
+template <int NC, int TX, int TY, bool TP, bool MO, int FE = 0, int CO = 0>
 __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __restrict__ h,
                                            float* __restrict__ hn, const float* __restrict__ D,
                                            float* __restrict__ Dn, unsigned* __restrict__ flags,
@@ -484,6 +571,7 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                                            float* __restrict__ abn = nullptr) {
     using T = FusedTile<NC, TX, TY, TP, MO>;
     static_assert(FE == 0 || MO, "the Cholesky integrator runs in the chained body only");
+    static_assert(CO == 0 || MO, "the MRT collision runs in the chained body only");
     static_assert(!MO || (TP && TX == 64), "next-level moments: two-pass body, one tile row per wavefront");
     static_assert(T::NH2 <= T::NT, "one R2 halo node per thread at most");
     static_assert(T::A1 <= 2 * T::NTH, "phase B covers the R1 region in two passes at most");
@@ -869,12 +957,20 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 const float w = ap == 1 ? wgt(1) : wgt(7);
                 const uint32_t hx = (uint32_t)wrapn(x0 + nlx, nx);  // halo column
                 const uint32_t bo = (zrow[1] + (uint32_t)(y0 + nly) * (uint32_t)nx + hx) * 4u;
-                const float hv = ld_off(hs + (size_t)(take_a ? ap : ap + 1) * N, bo);
                 const CollideIn in = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, (nly + 1) * T::W1 + nlx + 1,
                                                                 (nly + 2) * T::W2 + nlx + 2);
-                float pa, pb;
-                collide_pair_c(in, ex, ey, ez, w, hv, hv, pa, pb);
-                hval = take_a ? pa : pb;
+                if constexpr (CO == 1) {
+                    float hh[kQ];
+#pragma unroll
+                    for (int a = 0; a < kQ; ++a) hh[a] = ld_off(hs + (size_t)a * N, bo);
+                    const Mrt mc = mrt_coef(in, hh);
+                    hval = take_a ? mrt_post_c(in, mc, ex, ey, ez, w) : mrt_post_c(in, mc, -ex, -ey, -ez, w);
+                } else {
+                    const float hv = ld_off(hs + (size_t)(take_a ? ap : ap + 1) * N, bo);
+                    float pa, pb;
+                    collide_pair_c(in, ex, ey, ez, w, hv, hv, pa, pb);
+                    hval = take_a ? pa : pb;
+                }
             }
             float lin[5], rin[5];
 #pragma unroll
@@ -900,8 +996,10 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 const bool stx = ogx < nx;  // lanes past a ragged edge compute but do not store
                 float xv[kQ];               // MO: values leaving the row (c_y != 0), as stored
                 float check;
+                Mrt mo{};
+                if constexpr (CO == 1) mo = mrt_coef(own, hpop);
                 {
-                    const float post = collide_rest(own, hpop[0]);
+                    const float post = CO == 1 ? mrt_post(own, mo, 0) : collide_rest(own, hpop[0]);
                     if (store && stx) st_off(hns, bself, post);
                     check = post;
                     if constexpr (MO) add_moments(m0, 0, post);
@@ -909,7 +1007,12 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
 #pragma unroll
                 for (int a = 1; a < kQ; a += 2) {
                     float pp, pm;
-                    collide_pair(own, a, hpop[a], hpop[a + 1], pp, pm);
+                    if constexpr (CO == 1) {
+                        pp = mrt_post(own, mo, a);
+                        pm = mrt_post(own, mo, a + 1);
+                    } else {
+                        collide_pair(own, a, hpop[a], hpop[a + 1], pp, pm);
+                    }
                     check += pp + pm;
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
@@ -960,7 +1063,25 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                     const CollideIn hin = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, (hy + 1) * T::W1 + olx + 1,
                                                                      (hy + 2) * T::W2 + olx + 2);
                     float junk;
-                    if (hy < 0) {
+                    if constexpr (CO == 1) {
+                        float hh[kQ];
+#pragma unroll
+                        for (int a = 0; a < kQ; ++a) hh[a] = ld_off(hs + (size_t)a * N, bh);
+                        const Mrt mh = mrt_coef(hin, hh);
+                        if (hy < 0) {
+                            float s7 = __shfl_up(mrt_post(hin, mh, 7), 1, TX);
+                            if (left_edge) s7 = cl;
+                            float s10 = __shfl_down(mrt_post(hin, mh, 10), 1, TX);
+                            if (right_edge) s10 = cr;
+                            fold_up(mrt_post(hin, mh, 3), s7, s10, mrt_post(hin, mh, 15), mrt_post(hin, mh, 17), hj);
+                        } else {
+                            float s9 = __shfl_up(mrt_post(hin, mh, 9), 1, TX);
+                            if (left_edge) s9 = cl;
+                            float s8 = __shfl_down(mrt_post(hin, mh, 8), 1, TX);
+                            if (right_edge) s8 = cr;
+                            fold_dn(mrt_post(hin, mh, 4), s8, s9, mrt_post(hin, mh, 16), mrt_post(hin, mh, 18), hj);
+                        }
+                    } else if (hy < 0) {
                         const float h3 = ld_off(hs + (size_t)3 * N, bh), h7 = ld_off(hs + (size_t)7 * N, bh);
                         const float h10 = ld_off(hs + (size_t)10 * N, bh), h15 = ld_off(hs + (size_t)15 * N, bh);
                         const float h17 = ld_off(hs + (size_t)17 * N, bh);
@@ -1140,8 +1261,8 @@ __global__ __launch_bounds__(NC* TX* TY, NC == 2 ? 4 : 2) void k_fused2(
 // level n+1 to `mom_out`, so that step n+1 starts from them without a moments pass.
 // 64x8 tiles only (one tile row per wavefront); 156 KB of LDS for two components.
 // FE selects the FENE-P integrator (0 upwind/Euler, 1 Cholesky-log AB2, its rate history
-// read from ab and written to abn).
-template <int NC, int FE>
+// read from ab and written to abn); CO the collision (0 BGK, 1 MRT).
+template <int NC, int FE, int CO>
 __global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3(
     DevParams p, const float* __restrict__ h, float* __restrict__ hn, const float* __restrict__ D,
     float* __restrict__ Dn, const float* __restrict__ mom, float* __restrict__ mom_out, unsigned* __restrict__ flags,
@@ -1154,8 +1275,8 @@ __global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3(
     int tx_i, ty_i, zc_i;
     tile_of_block(blockIdx.x, gridDim.x, ntx, nty, gxw, gyh, tx_i, ty_i, zc_i);
     const int z0 = zc_i * zchunk;
-    fused_tile<NC, TX, TY, true, true, FE>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0,
-                                           min(z0 + zchunk, p.nz), mom, mom_out, ab, abn);
+    fused_tile<NC, TX, TY, true, true, FE, CO>(p, h, hn, D, Dn, flags, L, tx_i * TX, ty_i * TY, z0,
+                                               min(z0 + zchunk, p.nz), mom, mom_out, ab, abn);
 }
 
 // Many independent lattices in one launch: each workgroup takes one entry of the work
@@ -1222,20 +1343,24 @@ hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, 
     return launch_fused2_t<1, 32, 8>(p, b, zc, s);
 }
 
-template <int NC, int FE>
+template <int NC, int FE, int CO>
 static hipError_t launch_fused3_t(const DevParams& p, const Buffers& b, int zchunk, hipStream_t s) {
     const int ntx = (p.nx + 63) / 64, nty = (p.ny + 7) / 8;
     const int nzc = (p.nz + zchunk - 1) / zchunk;
     const int64_t nblk = (int64_t)ntx * nty * nzc;
-    hipLaunchKernelGGL((k_fused3<NC, FE>), dim3((unsigned)nblk), dim3(NC * 64 * 8), 0, s, p, b.h, b.hn, b.D, b.Dn,
+    hipLaunchKernelGGL((k_fused3<NC, FE, CO>), dim3((unsigned)nblk), dim3(NC * 64 * 8), 0, s, p, b.h, b.hn, b.D, b.Dn,
                        b.mom, b.mom_next, b.flags, zchunk, b.ab, b.ab_next);
     return hipGetLastError();
 }
 
 hipError_t launch_fused3(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s) {
     const int zc = t.zchunk > 0 ? t.zchunk : p.nz;
-    if (p.fene == 1) return p.nc == 2 ? launch_fused3_t<2, 1>(p, b, zc, s) : launch_fused3_t<1, 1>(p, b, zc, s);
-    return p.nc == 2 ? launch_fused3_t<2, 0>(p, b, zc, s) : launch_fused3_t<1, 0>(p, b, zc, s);
+    if (p.collision == 1) {
+        if (p.fene == 1) return p.nc == 2 ? launch_fused3_t<2, 1, 1>(p, b, zc, s) : launch_fused3_t<1, 1, 1>(p, b, zc, s);
+        return p.nc == 2 ? launch_fused3_t<2, 0, 1>(p, b, zc, s) : launch_fused3_t<1, 0, 1>(p, b, zc, s);
+    }
+    if (p.fene == 1) return p.nc == 2 ? launch_fused3_t<2, 1, 0>(p, b, zc, s) : launch_fused3_t<1, 1, 0>(p, b, zc, s);
+    return p.nc == 2 ? launch_fused3_t<2, 0, 0>(p, b, zc, s) : launch_fused3_t<1, 0, 0>(p, b, zc, s);
 }
 
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,

@@ -337,9 +337,14 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
                 emit(a, post);
             }
         } else {
+            // all 19 loads are issued before the first store (interleaving them per
+            // direction leaves few loads in flight)
+            float hv[kQ];
+#pragma unroll
+            for (int a = 0; a < kQ; ++a) hv[a] = hs[a * N + n];
 #pragma unroll
             for (int a = 0; a < kQ; ++a) {
-                const float ha = hs[a * N + n];
+                const float ha = hv[a];
                 float heq, src;
                 eq_src(a, heq, src);
                 const float post = ha - om * (ha - heq) + cf * src;

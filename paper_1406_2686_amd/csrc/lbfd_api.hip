@@ -191,10 +191,10 @@ int auto_zchunk(const lbfd_grid& g, int tile) {
 
 bool path_supports(const lbfd_ctx* c, int path) {
     if (path == LBFD_PATH_SPLIT) return true;
-    // MRT collides each node from all 19 of its populations, which the tile bodies do not
-    // hold for their halo nodes; the Cholesky integrator is in the chained body only
-    if (c->dp.collision == LBFD_COLLISION_MRT) return false;
-    if (c->dp.fene == LBFD_FENE_CHOLESKY_AB2) return path == LBFD_PATH_CHAINED;
+    // the MRT collision and the Cholesky integrator are in the chained tile body only (MRT
+    // collides each node from all 19 of its populations, halo nodes included)
+    if (c->dp.collision == LBFD_COLLISION_MRT || c->dp.fene == LBFD_FENE_CHOLESKY_AB2)
+        return path == LBFD_PATH_CHAINED;
     return true;
 }
 

@@ -418,12 +418,14 @@ def test_gpu_steady_shear_matches_lindner_closed_form(lb, Lam, coupling):
     assert np.allclose(u[0], -U + 2 * U * (Y + 0.5) / ny, atol=1e-4 * U)
 
 
+@pytest.mark.parametrize("path", ["chained", "split"])
 @pytest.mark.parametrize("case", ["droplet_visc_ratio", "couette_tau13", "droplet_stress_coupling"])
-def test_mrt_collision_matches_oracle(lb, case):
+def test_mrt_collision_matches_oracle(lb, case, path):
     """The multiple-relaxation-time collision (Sec. 2; bulk and shear modes at the local
-    tau, species momenta at tau_M = 1, other modes at 1) on the split path against the
-    oracle's MRT: a droplet with viscosity ratio 0.4 (tau_A = 0.62, tau_B = 1.1, so tau
-    varies across the interface), the FENE-P Couette at tau = 1.3, and the stress coupling."""
+    tau, species momenta at tau_M = 1, other modes at 1) in the chained one-launch step (its
+    default) and on the per-node split path against the oracle's MRT: a droplet with
+    viscosity ratio 0.4 (tau_A = 0.62, tau_B = 1.1, so tau varies across the interface), the
+    FENE-P Couette at tau = 1.3, and the stress coupling."""
     if case == "droplet_visc_ratio":
         wl = workloads.droplet_shear(nx=40, ny=24, nz=28, R=6.0, G=workloads.G_PHYSICS_1_004,
                                      polymer_phase="B", De=0.5, U=0.01, tau_A=0.62, tau_B=1.1)
@@ -436,7 +438,9 @@ def test_mrt_collision_matches_oracle(lb, case):
         steps = 400
     wl["params"]["collision"] = "mrt"
     lat = lb.from_workload(wl)
-    assert lat.get_tuning()["path"] == lb.PATH_SPLIT  # MRT runs on the split path
+    if path == "split":
+        lat.set_tuning(lb.PATH_SPLIT)
+    assert lat.get_tuning()["path"] == (lb.PATH_SPLIT if path == "split" else lb.PATH_CHAINED)
     lat.step(steps)
     g = lat.get_fields()
     dg = lat.diagnostics()
@@ -445,7 +449,7 @@ def test_mrt_collision_matches_oracle(lb, case):
     assert o.step(steps) == 0
     r = o.get_fields()
     do = o.diagnostics()
-    e = report(f"mrt-{case}", g, r)
+    e = report(f"mrt-{case}-{path}", g, r)
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
     for k in ("mass_A", "mass_B"):
         assert abs(dg[k] - do[k]) <= 1e-6 * abs(do[k]) + 1e-9
@@ -455,6 +459,40 @@ def test_mrt_collision_matches_oracle(lb, case):
         ob = oracle.from_workload(wl)
         assert ob.step(steps) == 0
         assert rel(ob.get_fields()[1], r[1]) > 100 * max(e["u"], 1e-7)
+
+
+@pytest.mark.parametrize("fene", ["upwind_euler", "cholesky_ab2"])
+def test_chained_options_agree_bitwise_across_zchunks_and_match_split(lb, fene):
+    """MRT in the chained step collides halo nodes (tile-edge lanes, neighbouring rows,
+    corners, the planes next to a z-chunk) from all 19 of their populations with the
+    function the node's own tile uses, so results are bitwise identical across z-chunks
+    (one plane per workgroup included).  Against the split path, which sums the
+    projection per direction and the moments in another order, they agree to FP32
+    rounding."""
+    wl = workloads.droplet_shear(nx=45, ny=19, nz=23, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="B", De=0.5, U=0.01, tau_A=0.7, tau_B=1.15)
+    wl["params"]["collision"] = "mrt"
+    wl["params"]["fene"] = fene
+    ref = None
+    for zc in (0, 1, 3, 7, 23):
+        lat = lb.from_workload(wl)
+        lat.set_tuning(lb.PATH_CHAINED, "64x8", zc)
+        lat.step(40)
+        f = lat.get_fields()
+        assert lat.flags() == 0
+        lat.close()
+        if ref is None:
+            ref = f
+        else:
+            for a, b in zip(f, ref):
+                assert np.array_equal(a, b), ("chained mrt", fene, zc)
+    lat = lb.from_workload(wl)
+    lat.set_tuning(lb.PATH_SPLIT)
+    lat.step(40)
+    t = lat.get_fields()
+    lat.close()
+    e = report(f"chained-mrt-vs-split-{fene}", ref, t)
+    assert e["u"] < 5e-6 and e["C"] < 1e-6 and e["rho"] < 1e-7
 
 
 def test_mrt_at_unit_tau_agrees_with_bgk_and_batches_refuse_it(lb):
@@ -514,42 +552,46 @@ def test_cholesky_ab2_fene_matches_oracle(lb, case, path):
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
 
 
-def test_mrt_with_cholesky_ab2_matches_oracle(lb):
-    """Both of the paper's options at once (MRT collision and the Cholesky-log integrator,
-    on the split path, the only one that has MRT) against the oracle with both."""
+@pytest.mark.parametrize("path", ["chained", "split"])
+def test_mrt_with_cholesky_ab2_matches_oracle(lb, path):
+    """Both of the paper's options at once (MRT collision and the Cholesky-log integrator)
+    against the oracle with both, in the chained step and on the split path."""
     wl = workloads.droplet_shear(nx=36, ny=20, nz=26, R=5.0, G=workloads.G_PHYSICS_1_004,
                                  polymer_phase="A", De=1.0, U=0.01, tau_A=0.7, tau_B=1.2)
     wl["params"]["collision"] = "mrt"
     wl["params"]["fene"] = "cholesky_ab2"
     wl["params"]["kappa"] = 0.01
     lat = lb.from_workload(wl)
-    assert lat.get_tuning()["path"] == lb.PATH_SPLIT
+    if path == "split":
+        lat.set_tuning(lb.PATH_SPLIT)
+    assert lat.get_tuning()["path"] == (lb.PATH_SPLIT if path == "split" else lb.PATH_CHAINED)
     lat.step(400)
     g = lat.get_fields()
     assert lat.flags() == 0
     lat.close()
     o = oracle.from_workload(wl)
     assert o.step(400) == 0
-    e = report("mrt+cholesky", g, o.get_fields())
+    e = report(f"mrt+cholesky-{path}", g, o.get_fields())
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
 
 
 def test_options_take_the_paths_that_implement_them(lb):
-    """A tuned path that lacks an option falls back to the split path (MRT: every tile path;
-    the Cholesky integrator: the single-pass and two-pass bodies).  The autotuner times only
+    """A tuned path that lacks an option falls back to the split path (the MRT collision and
+    the Cholesky integrator are in the chained tile body only).  The autotuner times only
     paths that implement the options and leaves the state, the rate history included,
     unchanged: a run that autotunes midway equals one that does not, bitwise."""
     wl = workloads.droplet_shear(nx=40, ny=20, nz=24, R=6.0, G=workloads.G_PHYSICS_1_004,
                                  polymer_phase="A", De=1.0, U=0.01)
     wc = dict(wl, params=dict(wl["params"], fene="cholesky_ab2"))
     wm = dict(wl, params=dict(wl["params"], collision="mrt"))
-    lat = lb.from_workload(wc)
-    for path, want in ((lb.PATH_FUSED, lb.PATH_SPLIT), (lb.PATH_TWOPASS, lb.PATH_SPLIT),
-                       (lb.PATH_CHAINED, lb.PATH_CHAINED), (lb.PATH_SPLIT, lb.PATH_SPLIT)):
-        lat.set_tuning(path, "64x8" if path == lb.PATH_CHAINED else "32x8", 0)
-        assert lat.get_tuning()["path"] == want
-    lat.close()
-    for w, want in ((wc, lb.PATH_CHAINED), (wm, lb.PATH_SPLIT)):
+    for w in (wc, wm):
+        lat = lb.from_workload(w)
+        for path, want in ((lb.PATH_FUSED, lb.PATH_SPLIT), (lb.PATH_TWOPASS, lb.PATH_SPLIT),
+                           (lb.PATH_CHAINED, lb.PATH_CHAINED), (lb.PATH_SPLIT, lb.PATH_SPLIT)):
+            lat.set_tuning(path, "64x8" if path == lb.PATH_CHAINED else "32x8", 0)
+            assert lat.get_tuning()["path"] == want
+        lat.close()
+    for w, want in ((wc, lb.PATH_CHAINED), (wm, lb.PATH_CHAINED)):
         a = lb.from_workload(w)
         a.step(7)
         before = a.get_fields()
