@@ -87,9 +87,11 @@ def build_lattice(lb, workloads, nx, ny, nz, zchunk=16, collision="bgk", fene="u
     return lat, wl0
 
 
-def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="upwind_euler"):
+def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="upwind_euler", keep=None):
     """FP64 oracle on a 96 x ny x 96 sub-box window of the same workload (same per-node
-    work), stepped until about `budget_s` seconds of CPU time have passed."""
+    work), stepped until about `budget_s` seconds of CPU time have passed.  With `keep` (a
+    dict), the window workload, the step count and the oracle's fields and diagnostics are
+    left in it for the FP32-vs-FP64 comparison."""
     import oracle
 
     bx = min(96, nx)
@@ -109,10 +111,39 @@ def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="up
         el = time.perf_counter() - t0
         if el >= budget_s or steps >= 50:
             break
+    if keep is not None:
+        keep.update(wl=wl, steps=steps, fields=o.get_fields(), diag=o.diagnostics(),
+                    desc=f"{bx}x{ny}x{bz} window at the centre of the {nx}x{ny}x{nz} droplet workload")
     return {"value": nodes * steps / el / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": f"{steps} steps of a {bx}x{ny}x{bz} window of the same droplet workload "
                       f"({nodes} nodes, FP64, {el:.1f} s)"}
+
+
+def fp32_vs_fp64(lb, ref, path_id):
+    """The GPU step (FP32, the launch path of the timed run) on the oracle's window, as
+    many steps as the oracle ran, against the oracle's FP64 fields: relative L2 and max
+    error of u, C and C - I, and the error of the deformation D."""
+    import numpy as np
+
+    lat = lb.from_workload(ref["wl"])
+    lat.set_tuning(path_id, "32x8" if path_id in (lb.PATH_FUSED, lb.PATH_SPLIT) else "64x8", 0)
+    lat.step(ref["steps"])
+    g = lat.get_fields()
+    dg = lat.diagnostics()
+    lat.close()
+    r = ref["fields"]
+    eye = np.array([1, 1, 1, 0, 0, 0], dtype=np.float64)[:, None]
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    return {"window": ref["desc"], "steps": ref["steps"],
+            "u_rel_l2": rel(g[1], r[1]), "u_max_abs": float(np.max(np.abs(g[1] - r[1]))),
+            "u_max": float(np.max(np.abs(r[1]))),
+            "C_rel_l2": rel(g[2], r[2]), "C_max_abs": float(np.max(np.abs(g[2] - r[2]))),
+            "CmI_rel_l2": rel(g[2] - eye, r[2] - eye),
+            "D_abs": abs(dg["D"] - ref["diag"]["D"]), "D": ref["diag"]["D"]}
 
 
 def copy_probe(torch, gib, reps=20):
@@ -426,7 +457,9 @@ def main():
     del lat
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(workloads, nx, ny, nz, collision=args.collision, fene=args.fene)
+        ref = {}
+        out["cpu_baseline"] = cpu_baseline(workloads, nx, ny, nz, collision=args.collision, fene=args.fene, keep=ref)
+        out["fp32_vs_fp64"] = fp32_vs_fp64(lb, ref, tuning["path"])
     print(json.dumps(out), flush=True)
 
 

@@ -650,9 +650,12 @@ def test_cholesky_ab2_steady_shear_and_restart(lb):
         lat.close()
 
 
-def test_full_size_droplet_sampled_window(lb):
+@pytest.mark.parametrize("collision,fene", [("bgk", "upwind_euler"), ("mrt", "upwind_euler"),
+                                           ("bgk", "cholesky_ab2"), ("mrt", "cholesky_ab2")])
+def test_full_size_droplet_sampled_window(lb, collision, fene):
     """The 1024x256x1024 droplet (268M nodes) in the launch configuration the benchmark
-    times, checked against the oracle on a sampled window.  One step moves information at
+    times (the chained step, with the default schemes and with the paper's MRT collision
+    and Cholesky-log integrator), checked against the oracle on a sampled window.  One step moves information at
     most two nodes (the Shan-Chen and stress-divergence stencils of the half-force
     velocity), so after k steps the centre of a window whose margin exceeds 2k is exact on
     a window-sized periodic oracle run.  The window straddles the droplet interface and
@@ -668,8 +671,10 @@ def test_full_size_droplet_sampled_window(lb):
     if free < need + (4 << 30):
         pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
     wl0 = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(0, nx, 0, 1))
+    wl0["params"].update(collision=collision, fene=fene)
     lat = lb.Lattice(nx, ny, nz, 2, wl0["params"])
     lat.set_walls(wl0["walls"]["u_bottom"], wl0["walls"]["u_top"])
+    assert lat.get_tuning()["path"] == lb.PATH_CHAINED
     for z0 in range(0, nz, 16):
         w = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(0, nx, z0, 16))
         lat.set_fields_box(0, 0, z0, nx, ny, 16, w["rho"], w["u"], w["C"])
@@ -687,6 +692,7 @@ def test_full_size_droplet_sampled_window(lb):
     del lat
     torch.cuda.empty_cache()
     wl = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(x0, bx, z0, bz))
+    wl["params"].update(collision=collision, fene=fene)
     o = oracle.from_workload(wl)
     assert o.step(steps) == 0
     r = o.get_fields()
@@ -695,7 +701,7 @@ def test_full_size_droplet_sampled_window(lb):
     sel = sel.ravel()
     gs = tuple(a[:, sel] for a in g)
     rs = tuple(a[:, sel] for a in r)
-    e = report("full-size window", gs, rs)
+    e = report(f"full-size window {collision}/{fene}", gs, rs)
     # the sample contains the interface: both phases are present
     assert rs[0][0].max() > 0.5 and rs[0][0].min() < 0.1
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
