@@ -238,11 +238,16 @@ lbfd_status lbfd_autotune(lbfd_ctx* ctx, int32_t reps, lbfd_tuning* best, double
 typedef struct lbfd_batch lbfd_batch;
 
 /* Steady test: D (Sec. 4.1 deformation) is sampled every `every` steps (even); an instance
- * is steady when |D(t) - D(t - window)| < tol (window a multiple of every). */
+ * is steady when |D(t - j window) - D(t - (j + 1) window)| < tol for j = 0 .. windows - 1
+ * (window a multiple of every; windows 0 counts as 1).  With one window the test is also
+ * met where D(t) passes through a slow extremum or plateau of a transient; two consecutive
+ * windows rule most of those out. */
 typedef struct {
     int32_t every;
     int32_t window;
     double tol;
+    int32_t windows;
+    int32_t reserved;   /* 0 */
 } lbfd_steady_crit;
 
 lbfd_status lbfd_batch_state_bytes(int32_t n, const lbfd_grid* grids, uint64_t* bytes);

@@ -113,7 +113,8 @@ _sig("lbfd_set_state", [_P, _P, ctypes.c_uint64])
 _sig("lbfd_set_tuning", [_P, ctypes.POINTER(Tuning)])
 _sig("lbfd_get_tuning", [_P, ctypes.POINTER(Tuning)])
 class SteadyCrit(ctypes.Structure):
-    _fields_ = [("every", ctypes.c_int32), ("window", ctypes.c_int32), ("tol", ctypes.c_double)]
+    _fields_ = [("every", ctypes.c_int32), ("window", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("windows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _sig("lbfd_autotune", [_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)])
@@ -445,8 +446,11 @@ class Batch:
         self._check(_lib.lbfd_batch_get_fields(self._h, i, _dp(rho), _dp(u), _dp(C)))
         return rho, u, C
 
-    def run_to_steady(self, every=100, window=1000, tol=1e-4, max_steps=100000):
-        crit = SteadyCrit(int(every), int(window), float(tol))
+    def run_to_steady(self, every=100, window=1000, tol=1e-4, max_steps=100000, windows=1):
+        """Step until each instance's D moved less than tol over each of the last `windows`
+        windows (or max_steps); returns final diagnostics and the steady step per instance
+        (-1 not steady, -2 fault)."""
+        crit = SteadyCrit(int(every), int(window), float(tol), int(windows), 0)
         d = (Diag * self.n)()
         ss = (ctypes.c_int64 * self.n)()
         self._check(_lib.lbfd_batch_run_to_steady(self._h, ctypes.byref(crit), int(max_steps), d, ss))

@@ -783,6 +783,16 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 const int t = wrapn(q - 2, nz);
                 const int st = ((q - 2) % 3 + 3) % 3;
                 const int st1 = ((q - 1) % 3 + 3) % 3;
+                const uint32_t bt = ((uint32_t)t * plane + own_xy) * 4u;
+                // the previous step's rate (Cholesky integrator), requested first so that
+                // its latency hides behind the stencil
+                float yp[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                if constexpr (FE == 1) {
+                    if (p.ab_hist) {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) yp[k] = ld_off(ab + (size_t)k * N, bt);
+                    }
+                }
                 float d0[6], u0[3];
 #pragma unroll
                 for (int k = 0; k < 6; ++k) d0[k] = L.cs[st][k][oi2];
@@ -870,13 +880,10 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                         dnew[kk] = d0[kk] + rate[kk];
                     }
                 }
-                const uint32_t bt = ((uint32_t)t * plane + own_xy) * 4u;
                 if constexpr (FE == 1) {
                     // the same rate taken through the Cholesky factor of f C, one AB2 step
                     if (den > 0.0f) {
-                        float yp[6], dn6[6], yd[6];
-#pragma unroll
-                        for (int k = 0; k < 6; ++k) yp[k] = p.ab_hist ? ld_off(ab + (size_t)k * N, bt) : 0.0f;
+                        float dn6[6], yd[6];
                         if (cholesky_ab2_step(p.L2, p.L2m3, d0, rate, yp, p.ab_hist != 0, dn6, yd)) {
 #pragma unroll
                             for (int k = 0; k < 6; ++k) {

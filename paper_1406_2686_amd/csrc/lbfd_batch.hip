@@ -358,7 +358,9 @@ lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit
     if (!b || !crit || !out || !steady_step || crit->every < 2 || crit->window < crit->every || !(crit->tol > 0))
         return LBFD_EINVAL;
     if ((crit->every & 1) || crit->window % crit->every) return bfail(b, LBFD_EINVAL, "every must be even, window a multiple of every");
+    if (crit->windows < 0 || crit->windows > 64) return bfail(b, LBFD_EINVAL, "windows must be in 0..64");
     const int lag = crit->window / crit->every;
+    const int nwin = crit->windows > 0 ? crit->windows : 1;
     std::vector<std::vector<double>> hist(b->n);
     for (int i = 0; i < b->n; ++i) steady_step[i] = -1;
     int64_t t = 0;
@@ -384,7 +386,10 @@ lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit
             if (st != LBFD_OK) return bfail(b, st, lbfd_last_error(b->inst[i]));
             hist[i].push_back(out[i].D);
             const size_t k = hist[i].size();
-            if ((int)k > lag && fabs(hist[i][k - 1] - hist[i][k - 1 - lag]) < crit->tol) {
+            bool steady = (int64_t)k > (int64_t)nwin * lag;
+            for (int j = 0; steady && j < nwin; ++j)
+                steady = fabs(hist[i][k - 1 - (size_t)j * lag] - hist[i][k - 1 - (size_t)(j + 1) * lag]) < crit->tol;
+            if (steady) {
                 act[i] = 0;
                 steady_step[i] = t;
             }

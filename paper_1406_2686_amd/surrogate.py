@@ -105,7 +105,8 @@ def warm_fields(wl: dict, D: float, theta_deg: float, amp: float):
     return rho, u, C
 
 
-def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256, warm=None, progress=None):
+def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256, warm=None, progress=None,
+          windows=1):
     """Batched solves to steady D.  ``warm``: optional list of (D, theta, amp) predictions
     (initial fields from warm_fields).  ``progress``: optional callable given a line of text
     after each chunk.  Returns per-case arrays and the wall time."""
@@ -121,7 +122,7 @@ def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256,
             part = [dict(w, **dict(zip(("rho", "u", "C"), warm_fields(w, *warm[s0 + i]))))
                     for i, w in enumerate(part)]
         b = lb.Batch(part)
-        diags, ss = b.run_to_steady(every=every, window=window, tol=tol, max_steps=max_steps)
+        diags, ss = b.run_to_steady(every=every, window=window, tol=tol, max_steps=max_steps, windows=windows)
         for i, (d, s) in enumerate(zip(diags, ss)):
             k = s0 + i
             out["D"][k] = d["D"]
@@ -139,8 +140,12 @@ def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256,
     return out
 
 
-def solve_plain(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, progress=None):
-    """Reference sweep: one lattice at a time, cold start, same steady test."""
+def solve_plain(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, progress=None, autotune=True,
+                windows=1):
+    """Reference sweep: one lattice at a time, cold start, same steady test as the batched
+    controller (D moved less than tol over each of the last `windows` windows).  With
+    ``autotune`` each lattice first picks its fastest launch shape (the autotuner's trial
+    launches leave the state unchanged; their time is part of the sweep's)."""
     import torch
 
     n = len(wls)
@@ -150,6 +155,8 @@ def solve_plain(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, prog
     t0 = time.perf_counter()
     for k, wl in enumerate(wls):
         lat = lb.from_workload(wl)
+        if autotune:
+            lat.autotune(reps=1)
         hist = []
         t = 0
         steps[k] = -1
@@ -161,7 +168,9 @@ def solve_plain(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, prog
                 steps[k] = -2
                 break
             hist.append(d["D"])
-            if len(hist) > lag and abs(hist[-1] - hist[-1 - lag]) < tol:
+            m = len(hist)
+            if m > windows * lag and all(abs(hist[m - 1 - j * lag] - hist[m - 1 - (j + 1) * lag]) < tol
+                                         for j in range(windows)):
                 steps[k] = t
                 break
         D[k] = d["D"]

@@ -161,7 +161,8 @@ def test_autotuners_pick_a_shape_and_leave_the_state_unchanged(lb):
 def test_run_to_steady_retires_converged_instances(lb):
     """A uniform mixture (phi = 0 everywhere, so no droplet and D = 0) is steady at the
     first test; a sheared droplet keeps deforming.  The controller reports the step at
-    which each met |D(t) - D(t - window)| < tol and stops advancing it."""
+    which each met |D(t) - D(t - window)| < tol (over one window, or each of several
+    consecutive ones) and stops advancing it."""
     still = workloads.droplet_shear(nx=24, ny=12, nz=16, R=3.0, rho_in=0.5, rho_out=0.5, G=0.0,
                                     polymer_phase="none", U=0.01)
     moving = workloads.droplet_shear(nx=48, ny=24, nz=32, R=6.0, G=workloads.G_PHYSICS_1_004,
@@ -172,4 +173,13 @@ def test_run_to_steady_retires_converged_instances(lb):
     assert diags[0]["step"] == ss[0]
     assert ss[1] == -1 or ss[1] > ss[0]
     assert diags[1]["step"] == (200 if ss[1] == -1 else ss[1])
+    b.close()
+    # two consecutive windows: five samples for the still mixture; the sheared droplet
+    # never qualifies earlier than under one window
+    b = lb.Batch([still, moving])
+    diags2, ss2 = b.run_to_steady(every=10, window=20, tol=1e-6, max_steps=200, windows=2)
+    assert ss2[0] == 50 and diags2[0]["step"] == 50
+    assert ss2[1] == -1 or (ss[1] != -1 and ss2[1] >= ss[1])
+    with pytest.raises(lb.LbfdError):
+        b.run_to_steady(every=10, window=20, tol=1e-6, max_steps=20, windows=-1)
     b.close()
