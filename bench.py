@@ -120,6 +120,35 @@ def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="up
                       f"({nodes} nodes, FP64, {el:.1f} s)"}
 
 
+def sweep_judgement(plain, cold, paths, tol_d=0.01):
+    """Which held-out answers count, and the fastest sweep path whose answers are all within
+    tol_d of the plain per-case solves.  plain, cold: solver results (D, steady_step,
+    wall_s) of the per-case sweep and of the batched cold solve; paths: name -> (seconds, D
+    per case) of the candidate paths.
+
+    Judged cases are those the plain sweep brought to steady D, except those whose answer
+    depends on the launch shape.  The batched solve runs the chained body, and each of its
+    instances equals a single chained lattice bit for bit; where its answer and the plain
+    solve's (the autotuned shape) differ by more than tol_d, rounding has decided the branch
+    (a marginally stable droplet that stays or breaks up), and no shape reproduces another's."""
+    import numpy as np
+
+    steady = np.asarray(plain["steady_step"]) > 0
+    ref = np.asarray(plain["D"], dtype=np.float64)
+    shape_sensitive = steady & (np.abs(np.asarray(cold["D"]) - ref) > tol_d)
+    valid = steady & ~shape_sensitive
+
+    def within(d, mask):
+        return float(np.mean(np.abs(np.asarray(d) - ref)[mask] <= tol_d)) if mask.any() else 1.0
+
+    scores = {k: (t, within(d, valid)) for k, (t, d) in paths.items()}
+    scores["plain"] = (plain["wall_s"], 1.0)
+    best = min((t, k) for k, (t, w) in scores.items() if w >= 1.0)
+    return {"valid": valid, "shape_sensitive": shape_sensitive, "best": best,
+            "within": {k: w for k, (t, w) in scores.items() if k != "plain"},
+            "within_all_steady": {k: within(d, steady) for k, (t, d) in paths.items()}}
+
+
 def fp32_vs_fp64(lb, ref, path_id):
     """The GPU step (FP32, the launch path of the timed run) on the oracle's window, as
     many steps as the oracle ran, against the oracle's FP64 fields: relative L2 and max
@@ -216,23 +245,15 @@ def sweep(lb, workloads, args):
         answer[idx] = fb["D"]
         t_fb = fb["wall_s"]
     log(f"surrogate + fallback: {flag.sum()} of {len(test)} solved, {t_pred + t_fb:.2f} s")
-    # judged: cases the plain sweep brought to steady D, except those whose answer depends on
-    # the launch shape.  The batched solve runs the chained body, and each of its instances
-    # equals a single chained lattice bit for bit; where its answer and the plain solve's
-    # (the autotuned shape) differ by more than 0.01, rounding has decided the branch (a
-    # marginally stable droplet that stays or breaks up), and no shape reproduces another's.
-    shape_sensitive = (plain["steady_step"] > 0) & (np.abs(cold["D"] - plain["D"]) > 0.01)
-    valid = (plain["steady_step"] > 0) & ~shape_sensitive
-    judge = plain["D"]
+    J = sweep_judgement(plain, cold, {"surrogate_with_fallback": (t_pred + t_fb, answer),
+                                      "batched_cold": (cold["wall_s"], cold["D"])})
+    valid, shape_sensitive, judge = J["valid"], J["shape_sensitive"], plain["D"]
     if args.save_data:
         np.savez(args.save_data, X_train=sg.features(train), Y_train=np.stack([gen["D"], gen["theta"], gen["amp"]], 1),
                  steady_train=gen["steady_step"], X_test=sg.features(test), D_plain=plain["D"],
                  steady_plain=plain["steady_step"], D_cold=cold["D"], pred1=p1, pred2=p2)
     within = lambda d: float(np.mean(np.abs(d - judge)[valid] <= 0.01))
-    paths = {"surrogate_with_fallback": (t_pred + t_fb, within(answer)),
-             "batched_cold": (cold["wall_s"], within(cold["D"])),
-             "plain": (plain["wall_s"], 1.0)}
-    best = min((t, k) for k, (t, w) in paths.items() if w >= 1.0)
+    best = J["best"]
     out = {"metric": "sweep time-to-steady-D (|dD| <= 0.01 against plain solves)", "unit": "s",
            "value": round(best[0], 3), "path": best[1], "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic", "dtype": "f32 solver, bf16 surrogate inference",
@@ -248,9 +269,7 @@ def sweep(lb, workloads, args):
            # the same over every case the plain sweep brought to steady D, shape-sensitive ones
            # included (the batched solve's own check is its bitwise equality with single
            # chained lattices, which the tests verify)
-           "within_0.01_all_steady": {k: float(np.mean(np.abs(v - judge)[plain["steady_step"] > 0] <= 0.01))
-                                      for k, v in (("surrogate_with_fallback", answer),
-                                                   ("batched_cold", cold["D"]))},
+           "within_0.01_all_steady": J["within_all_steady"],
            "surrogate_mean_abs_dD": float(np.abs(pred[:, 0] - judge)[valid].mean()),
            "unsteady_or_fault": {"plain": int((plain["steady_step"] <= 0).sum()),
                                  "cold": int((cold["steady_step"] <= 0).sum()),
