@@ -370,8 +370,8 @@ def mlp_bench(lb, workloads, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--grid", type=str, default="1024x256x1024")
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--path", choices=["default", "chained", "two-pass", "fused", "split"], default="default",

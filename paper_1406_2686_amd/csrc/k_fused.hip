@@ -433,23 +433,6 @@ struct Mrt {
     float e, xx, ww, xy, yz, xz;
 };
 
-// E and S of direction (ex, ey, ez) with weight w (the stress term of eq. MODEtransformation
-// in E when the stress coupling is on)
-__device__ __forceinline__ void mrt_eq_src(const CollideIn& c, float ex, float ey, float ez, float w, float& E,
-                                           float& S) {
-#pragma clang fp contract(off)
-    const float cu = fmaf(ez, c.u[2], fmaf(ey, c.u[1], ex * c.u[0]));
-    const float cF = fmaf(ez, c.F[2], fmaf(ey, c.F[1], ex * c.F[0]));
-    float ee = w * fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs);
-    if (c.stress) {
-        const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
-                          2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
-        ee = fmaf(-4.5f * w, cTc - c.trs3, ee);
-    }
-    E = ee + ((3.0f * w) * c.rs) * cu;
-    S = w * fmaf(9.0f * cu, cF, -3.0f * c.uF) + (3.0f * w) * cF;
-}
-
 // the projection coefficients of a node from its 19 populations h.  The coefficients are
 // moments of g = f - E + S/2 of order two and below, and the lattice's fourth-order
 // isotropy gives those of E and S in closed form:
@@ -488,24 +471,38 @@ __device__ __forceinline__ Mrt mrt_coef(const CollideIn& c, const float (&h)[kQ]
                (gyy - gzz) * (k2 * (1.0f / 12.0f)), gxy * (k2 * 0.25f), gyz * (k2 * 0.25f), gxz * (k2 * 0.25f)};
 }
 
-// post-collision population of direction (ex, ey, ez) (a run-time or compile-time value:
-// the rows are exact small integers either way)
-__device__ __forceinline__ float mrt_post_c(const CollideIn& c, const Mrt& m, float ex, float ey, float ez, float w) {
+// Post-collision populations of the opposite pair c_a = (ex, ey, ez), c_b = -c_a (a run-time
+// or compile-time direction: the rows are exact small integers either way).  The
+// equilibrium and the source split into parts even and odd in c, and the mode sum
+// (1 - 1/tau) P2 g is even in c, so the pair shares everything but the odd parts.
+__device__ __forceinline__ void mrt_pair_c(const CollideIn& c, const Mrt& m, float ex, float ey, float ez, float w,
+                                           float& pa, float& pb) {
 #pragma clang fp contract(off)
-    float E, S;
-    mrt_eq_src(c, ex, ey, ez, w, E, S);
+    const float cu = fmaf(ez, c.u[2], fmaf(ey, c.u[1], ex * c.u[0]));
+    const float cF = fmaf(ez, c.F[2], fmaf(ey, c.F[1], ex * c.F[0]));
+    float ee = w * fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs);  // equilibrium, even part
+    if (c.stress) {
+        const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
+                          2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
+        ee = fmaf(-4.5f * w, cTc - c.trs3, ee);
+    }
+    const float eo = ((3.0f * w) * c.rs) * cu;                 // equilibrium, odd part
+    const float se = w * fmaf(9.0f * cu, cF, -3.0f * c.uF);    // source, even part
+    const float so = (3.0f * w) * cF;                          // source, odd part
     const float c2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
-    float post = fmaf(0.5f, S, E);
-    post = fmaf(fmaf(19.0f, c2, -30.0f), m.e, post);
-    post = fmaf(fmaf(3.0f * ex, ex, -c2), m.xx, post);
-    post = fmaf(fmaf(ey, ey, -(ez * ez)), m.ww, post);
-    post = fmaf(ex * ey, m.xy, post);
-    post = fmaf(ey * ez, m.yz, post);
-    post = fmaf(ex * ez, m.xz, post);
-    return post;
+    float r = fmaf(19.0f, c2, -30.0f) * m.e;
+    r = fmaf(fmaf(3.0f * ex, ex, -c2), m.xx, r);
+    r = fmaf(fmaf(ey, ey, -(ez * ez)), m.ww, r);
+    r = fmaf(ex * ey, m.xy, r);
+    r = fmaf(ey * ez, m.yz, r);
+    r = fmaf(ex * ez, m.xz, r);
+    const float ev = fmaf(0.5f, se, ee) + r;
+    const float od = fmaf(0.5f, so, eo);
+    pa = ev + od;
+    pb = ev - od;
 }
-__device__ __forceinline__ float mrt_post(const CollideIn& c, const Mrt& m, int a) {
-    return mrt_post_c(c, m, float(cx(a)), float(cy(a)), float(cz(a)), wgt(a));
+__device__ __forceinline__ void mrt_pair(const CollideIn& c, const Mrt& m, int a, float& pa, float& pb) {
+    mrt_pair_c(c, m, float(cx(a)), float(cy(a)), float(cz(a)), wgt(a), pa, pb);
 }
 
 // the pairs with c_x != 0 (their odd member has c_x = +1): 1, 7, 9, 11, 13
@@ -971,7 +968,9 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
 #pragma unroll
                     for (int a = 0; a < kQ; ++a) hh[a] = ld_off(hs + (size_t)a * N, bo);
                     const Mrt mc = mrt_coef(in, hh);
-                    hval = take_a ? mrt_post_c(in, mc, ex, ey, ez, w) : mrt_post_c(in, mc, -ex, -ey, -ez, w);
+                    float pa, pb;
+                    mrt_pair_c(in, mc, ex, ey, ez, w, pa, pb);
+                    hval = take_a ? pa : pb;
                 } else {
                     const float hv = ld_off(hs + (size_t)(take_a ? ap : ap + 1) * N, bo);
                     float pa, pb;
@@ -1006,7 +1005,13 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 Mrt mo{};
                 if constexpr (CO == 1) mo = mrt_coef(own, hpop);
                 {
-                    const float post = CO == 1 ? mrt_post(own, mo, 0) : collide_rest(own, hpop[0]);
+                    float post;
+                    if constexpr (CO == 1) {
+                        float junk;
+                        mrt_pair(own, mo, 0, post, junk);
+                    } else {
+                        post = collide_rest(own, hpop[0]);
+                    }
                     if (store && stx) st_off(hns, bself, post);
                     check = post;
                     if constexpr (MO) add_moments(m0, 0, post);
@@ -1015,8 +1020,7 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 for (int a = 1; a < kQ; a += 2) {
                     float pp, pm;
                     if constexpr (CO == 1) {
-                        pp = mrt_post(own, mo, a);
-                        pm = mrt_post(own, mo, a + 1);
+                        mrt_pair(own, mo, a, pp, pm);
                     } else {
                         collide_pair(own, a, hpop[a], hpop[a + 1], pp, pm);
                     }
@@ -1075,18 +1079,24 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
 #pragma unroll
                         for (int a = 0; a < kQ; ++a) hh[a] = ld_off(hs + (size_t)a * N, bh);
                         const Mrt mh = mrt_coef(hin, hh);
+                        float p3, p4, p7, p8, p9, p10, p15, p16, p17, p18;
+                        mrt_pair(hin, mh, 3, p3, p4);
+                        mrt_pair(hin, mh, 7, p7, p8);
+                        mrt_pair(hin, mh, 9, p9, p10);
+                        mrt_pair(hin, mh, 15, p15, p16);
+                        mrt_pair(hin, mh, 17, p17, p18);
                         if (hy < 0) {
-                            float s7 = __shfl_up(mrt_post(hin, mh, 7), 1, TX);
+                            float s7 = __shfl_up(p7, 1, TX);
                             if (left_edge) s7 = cl;
-                            float s10 = __shfl_down(mrt_post(hin, mh, 10), 1, TX);
+                            float s10 = __shfl_down(p10, 1, TX);
                             if (right_edge) s10 = cr;
-                            fold_up(mrt_post(hin, mh, 3), s7, s10, mrt_post(hin, mh, 15), mrt_post(hin, mh, 17), hj);
+                            fold_up(p3, s7, s10, p15, p17, hj);
                         } else {
-                            float s9 = __shfl_up(mrt_post(hin, mh, 9), 1, TX);
+                            float s9 = __shfl_up(p9, 1, TX);
                             if (left_edge) s9 = cl;
-                            float s8 = __shfl_down(mrt_post(hin, mh, 8), 1, TX);
+                            float s8 = __shfl_down(p8, 1, TX);
                             if (right_edge) s8 = cr;
-                            fold_dn(mrt_post(hin, mh, 4), s8, s9, mrt_post(hin, mh, 16), mrt_post(hin, mh, 18), hj);
+                            fold_dn(p4, s8, s9, p16, p18, hj);
                         }
                     } else if (hy < 0) {
                         const float h3 = ld_off(hs + (size_t)3 * N, bh), h7 = ld_off(hs + (size_t)7 * N, bh);
