@@ -71,12 +71,13 @@ def recorded_traffic(workload, path_id, default_options=True):
     return rec
 
 
-def build_lattice(lb, workloads, nx, ny, nz, zchunk=16, collision="bgk", fene="upwind_euler"):
+def build_lattice(lb, workloads, nx, ny, nz, zchunk=16, collision="bgk", fene="upwind_euler", coupling="force"):
     """Create the droplet lattice and upload its fields slab by slab (host memory stays
     bounded for the 268M-node grid)."""
     wl0 = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(0, nx, 0, 1))
     wl0["params"]["collision"] = collision
     wl0["params"]["fene"] = fene
+    wl0["params"]["coupling"] = coupling
     lat = lb.Lattice(nx, ny, nz, 2, wl0["params"])
     lat.set_walls(wl0["walls"]["u_bottom"], wl0["walls"]["u_top"])
     for z0 in range(0, nz, zchunk):
@@ -87,7 +88,8 @@ def build_lattice(lb, workloads, nx, ny, nz, zchunk=16, collision="bgk", fene="u
     return lat, wl0
 
 
-def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="upwind_euler", keep=None):
+def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="upwind_euler", keep=None,
+                 coupling="force"):
     """FP64 oracle on a 96 x ny x 96 sub-box window of the same workload (same per-node
     work), stepped until about `budget_s` seconds of CPU time have passed.  With `keep` (a
     dict), the window workload, the step count and the oracle's fields and diagnostics are
@@ -101,6 +103,7 @@ def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="up
     wl = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(x0, bx, z0, bz))
     wl["params"]["collision"] = collision
     wl["params"]["fene"] = fene
+    wl["params"]["coupling"] = coupling
     o = oracle.from_workload(wl)
     nodes = bx * ny * bz
     steps = 0
@@ -413,6 +416,8 @@ def main():
                     help="launch path of the step (default: the library's, the chained step)")
     ap.add_argument("--collision", choices=["bgk", "mrt"], default="bgk",
                     help="collision operator (MRT runs on the split path)")
+    ap.add_argument("--coupling", choices=["force", "stress"], default="force",
+                    help="polymer stress as a body force (default) or in the equilibrium's second moment")
     ap.add_argument("--fene", choices=["upwind_euler", "cholesky_ab2"], default="upwind_euler",
                     help="FENE-P integrator (the Cholesky scheme runs on the split path)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -458,7 +463,8 @@ def main():
     N = nx * ny * nz
     torch.cuda.set_device(0)
     t_init = time.perf_counter()
-    lat, wl0 = build_lattice(lb, workloads, nx, ny, nz, collision=args.collision, fene=args.fene)
+    lat, wl0 = build_lattice(lb, workloads, nx, ny, nz, collision=args.collision, fene=args.fene,
+                             coupling=args.coupling)
     torch.cuda.synchronize()
     log(f"init {nx}x{ny}x{nz}: {time.perf_counter() - t_init:.1f} s")
 
@@ -503,7 +509,7 @@ def main():
     alg = alg_node * N
     achieved = alg / (step_ms * 1e-3) / 1e9
     rec = recorded_traffic(f"droplet_shear_{nx}x{ny}x{nz}", tuning["path"],
-                           args.collision == "bgk" and args.fene == "upwind_euler")
+                           args.collision == "bgk" and args.fene == "upwind_euler" and args.coupling == "force")
     traffic = None if rec is None else round(rec["bytes_per_step"] / (step_ms * 1e-3) / 1e9, 1)
     mass_drift = max(abs(d1["mass_A"] - d0["mass_A"]) / d0["mass_A"],
                      abs(d1["mass_B"] - d0["mass_B"]) / d0["mass_B"])
@@ -515,7 +521,7 @@ def main():
         "config": {"workload": f"droplet_shear_{nx}x{ny}x{nz}", "nodes": N, "ncomp": 2,
                    "launch": {"path": ["fused", "split", "two-pass", "chained"][tuning["path"]], "tile": tuning["tile"],
                               "zchunk": tuning["zchunk"]},
-                   "collision": args.collision, "fene": args.fene,
+                   "collision": args.collision, "fene": args.fene, "coupling": args.coupling,
                    "droplet_R": wl0["meta"]["R"], "polymer": "matrix (L2=400, De=1)",
                    "diag_every": args.diag_every, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -532,7 +538,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         ref = {}
-        out["cpu_baseline"] = cpu_baseline(workloads, nx, ny, nz, collision=args.collision, fene=args.fene, keep=ref)
+        out["cpu_baseline"] = cpu_baseline(workloads, nx, ny, nz, collision=args.collision, fene=args.fene, keep=ref,
+                                           coupling=args.coupling)
         out["fp32_vs_fp64"] = fp32_vs_fp64(lb, ref, tuning["path"])
     print(json.dumps(out), flush=True)
 

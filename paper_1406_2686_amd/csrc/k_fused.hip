@@ -9,11 +9,14 @@
 //   B  computes, for plane q-1 on the tile plus a 1-node halo, the Shan-Chen force
 //      (eq. SCforce), the central divergence of T, the species split F_s = g_s +
 //      (rho_s/rho) F_p and the half-force velocity u (eq. equilibrium:vel);
-//   C  collides plane q-1 (BGK with the forcing source, eq. LB with Lambda = I/tau(phi))
+//   C  collides plane q-1 (BGK with the forcing source, eq. LB with Lambda = I/tau(phi);
+//      in the chained body, the multiple-relaxation-time collision of Sec. 2 as an option)
 //      and pushes the post-collision populations to their neighbours, bouncing links that
 //      leave through a wall back with the moving-wall correction;
 //   D  advances C on plane q-2 with the explicit FENE-P update (eq. FENE): first-order
-//      upwind advection, G^T C + C G with central G_ij = d_i u_j, Peterlin relaxation.
+//      upwind advection, G^T C + C G with central G_ij = d_i u_j, Peterlin relaxation (in
+//      the chained body, the Cholesky-log Adams-Bashforth-2 integrator of Sec. 2 with
+//      central differences and artificial diffusivity as an option).
 // Every stage reads time level n only, so HBM sees each population and C component read
 // once and written once per step: 2 x ncomp x 19 x 4 + 2 x 6 x 4 bytes per node.  The halo
 // re-reads of neighbouring tiles are meant to hit a cache: blocks are mapped so that the

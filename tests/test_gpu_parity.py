@@ -575,6 +575,28 @@ def test_mrt_with_cholesky_ab2_matches_oracle(lb, path):
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
 
 
+def test_papers_full_scheme_matches_oracle(lb):
+    """The paper's own scheme throughout, in the chained one-launch step: MRT collision,
+    polymer stress through the equilibrium's second moment, and the Cholesky-log
+    Adams-Bashforth-2 integrator with artificial diffusivity, against the oracle with the
+    same three options on a ragged droplet grid."""
+    wl = workloads.droplet_shear(nx=37, ny=21, nz=29, R=6.0, G=workloads.G_PHYSICS_1_004,
+                                 polymer_phase="A", De=1.0, U=0.01, tau_A=0.8, coupling="stress")
+    wl["params"].update(collision="mrt", fene="cholesky_ab2", kappa=0.01)
+    lat = lb.from_workload(wl)
+    assert lat.get_tuning()["path"] == lb.PATH_CHAINED
+    lat.step(500)
+    g = lat.get_fields()
+    dg = lat.diagnostics()
+    assert lat.flags() == 0
+    lat.close()
+    o = oracle.from_workload(wl)
+    assert o.step(500) == 0
+    e = report("paper-scheme", g, o.get_fields())
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
+    assert abs(dg["D"] - o.diagnostics()["D"]) < 1e-5
+
+
 def test_options_take_the_paths_that_implement_them(lb):
     """A tuned path that lacks an option falls back to the split path (the MRT collision and
     the Cholesky integrator are in the chained tile body only).  The autotuner times only
@@ -650,12 +672,14 @@ def test_cholesky_ab2_steady_shear_and_restart(lb):
         lat.close()
 
 
-@pytest.mark.parametrize("collision,fene", [("bgk", "upwind_euler"), ("mrt", "upwind_euler"),
-                                           ("bgk", "cholesky_ab2"), ("mrt", "cholesky_ab2")])
-def test_full_size_droplet_sampled_window(lb, collision, fene):
+@pytest.mark.parametrize("collision,fene,coupling", [
+    ("bgk", "upwind_euler", "force"), ("mrt", "upwind_euler", "force"), ("bgk", "cholesky_ab2", "force"),
+    ("mrt", "cholesky_ab2", "force"), ("mrt", "cholesky_ab2", "stress")])
+def test_full_size_droplet_sampled_window(lb, collision, fene, coupling):
     """The 1024x256x1024 droplet (268M nodes) in the launch configuration the benchmark
-    times (the chained step, with the default schemes and with the paper's MRT collision
-    and Cholesky-log integrator), checked against the oracle on a sampled window.  One step moves information at
+    times (the chained step, with the default schemes, with the paper's MRT collision and
+    Cholesky-log integrator, and with the paper's whole scheme including the stress in the
+    equilibrium), checked against the oracle on a sampled window.  One step moves information at
     most two nodes (the Shan-Chen and stress-divergence stencils of the half-force
     velocity), so after k steps the centre of a window whose margin exceeds 2k is exact on
     a window-sized periodic oracle run.  The window straddles the droplet interface and
@@ -671,7 +695,7 @@ def test_full_size_droplet_sampled_window(lb, collision, fene):
     if free < need + (4 << 30):
         pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
     wl0 = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(0, nx, 0, 1))
-    wl0["params"].update(collision=collision, fene=fene)
+    wl0["params"].update(collision=collision, fene=fene, coupling=coupling)
     lat = lb.Lattice(nx, ny, nz, 2, wl0["params"])
     lat.set_walls(wl0["walls"]["u_bottom"], wl0["walls"]["u_top"])
     assert lat.get_tuning()["path"] == lb.PATH_CHAINED
@@ -692,7 +716,7 @@ def test_full_size_droplet_sampled_window(lb, collision, fene):
     del lat
     torch.cuda.empty_cache()
     wl = workloads.droplet_cfg2(nx=nx, ny=ny, nz=nz, box=(x0, bx, z0, bz))
-    wl["params"].update(collision=collision, fene=fene)
+    wl["params"].update(collision=collision, fene=fene, coupling=coupling)
     o = oracle.from_workload(wl)
     assert o.step(steps) == 0
     r = o.get_fields()
@@ -701,7 +725,7 @@ def test_full_size_droplet_sampled_window(lb, collision, fene):
     sel = sel.ravel()
     gs = tuple(a[:, sel] for a in g)
     rs = tuple(a[:, sel] for a in r)
-    e = report(f"full-size window {collision}/{fene}", gs, rs)
+    e = report(f"full-size window {collision}/{fene}/{coupling}", gs, rs)
     # the sample contains the interface: both phases are present
     assert rs[0][0].max() > 0.5 and rs[0][0].min() < 0.1
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
