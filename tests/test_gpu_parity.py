@@ -102,10 +102,12 @@ def test_droplet_long_runs(lb, case):
     assert abs(dg["D"] - do["D"]) < 1e-5
 
 
+@pytest.mark.parametrize("scheme", ["default", "paper"])
 @pytest.mark.parametrize("shape", [(1, 3, 1), (5, 3, 2), (65, 7, 3), (3, 9, 70)])
-def test_degenerate_and_ragged_shapes(lb, shape):
+def test_degenerate_and_ragged_shapes(lb, shape, scheme):
     """Minimal wall gap (ny = 3), single-node periodic directions and tails that do
-    not fill a 256-thread block."""
+    not fill a 256-thread block, with the default schemes and with the paper's scheme
+    throughout (MRT, stress in the equilibrium, Cholesky-log integrator)."""
     nx, ny, nz = shape
     rho, u, C = workloads.random_state(nx, ny, nz, 2, seed=nx * 100 + nz, amp_rho=0.05,
                                        amp_u=0.01, amp_C=0.1)
@@ -115,9 +117,56 @@ def test_degenerate_and_ragged_shapes(lb, shape):
                      "polymer_phase": "A", "eta_p": 0.1, "tau_p": 50.0, "L2": 60.0},
           "walls": {"u_bottom": [-0.01, 0, 0.005], "u_top": [0.01, 0, -0.002]},
           "rho": rho, "u": u, "C": C}
+    if scheme == "paper":
+        wl["params"].update(collision="mrt", fene="cholesky_ab2", kappa=0.01, coupling="stress")
     g, r, _, _ = run_both(lb, wl, 60)
-    e = report(f"shape{shape}", g, r)
+    e = report(f"shape{shape}-{scheme}", g, r)
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+
+
+def test_random_configurations_match_oracle(lb):
+    """Seeded random configurations: extents (ragged, ny = 3, nz = 1), one or two
+    components, polymer phase, relaxation times, wall velocities, the three options, and
+    the launch path, tile and z-chunk (a path without an option steps on the split
+    path), each against the oracle after 50 steps."""
+    rng = np.random.default_rng(20261203)
+    for k in range(12):
+        nx = int(rng.integers(1, 80))
+        ny = int(rng.integers(3, 24))
+        nz = int(rng.integers(1, 40))
+        nc = int(rng.integers(1, 3))
+        rho, u, C = workloads.random_state(nx, ny, nz, nc, seed=1000 + k, amp_rho=0.05, amp_u=0.01, amp_C=0.1)
+        if nc == 2:
+            rho[0] += 0.5
+        params = {"tau_A": float(rng.uniform(0.6, 1.5)), "tau_B": float(rng.uniform(0.6, 1.5)),
+                  "G": float(rng.uniform(0.0, 1.5)) if nc == 2 else 0.0, "delta": 0.1,
+                  "rho0": [1.5, 1.0] if nc == 2 else [1.0, 0.0],
+                  "polymer_phase": str(rng.choice(["A", "B", "all", "none"])) if nc == 2 else "all",
+                  "eta_p": float(rng.uniform(0.0, 0.1)), "tau_p": float(rng.uniform(20, 200)),
+                  "L2": float(rng.choice([30.0, 100.0, 400.0])),
+                  "collision": str(rng.choice(["bgk", "mrt"])), "fene": str(rng.choice(["upwind_euler", "cholesky_ab2"])),
+                  "kappa": float(rng.choice([0.0, 0.01])), "coupling": str(rng.choice(["force", "stress"]))}
+        walls = {"u_bottom": [float(rng.uniform(-0.02, 0.02)), 0.0, float(rng.uniform(-0.01, 0.01))],
+                 "u_top": [float(rng.uniform(-0.02, 0.02)), 0.0, float(rng.uniform(-0.01, 0.01))]}
+        wl = {"grid": {"nx": nx, "ny": ny, "nz": nz, "ncomp": nc}, "params": params, "walls": walls,
+              "rho": rho, "u": u, "C": C}
+        path = int(rng.choice([lb.PATH_FUSED, lb.PATH_SPLIT, lb.PATH_TWOPASS, lb.PATH_CHAINED]))
+        tile = str(rng.choice(["32x8", "16x16", "64x8"])) if path == lb.PATH_TWOPASS else (
+            "64x8" if path == lb.PATH_CHAINED else str(rng.choice(["32x8", "16x16"])))
+        zc = int(rng.choice([0, 1, 3, 8]))
+        tag = f"random{k} {nx}x{ny}x{nz} nc={nc} path={path} {tile} zc={zc} " + \
+              " ".join(f"{key}={params[key]}" for key in ("collision", "fene", "coupling", "polymer_phase"))
+        print(tag, flush=True)
+        lat = lb.from_workload(wl)
+        lat.set_tuning(path, tile, zc)
+        lat.step(50)
+        g = lat.get_fields()
+        assert lat.flags() == 0, tag
+        lat.close()
+        o = oracle.from_workload(wl)
+        assert o.step(50) == 0, tag
+        e = report(tag, g, o.get_fields())
+        assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5, tag
 
 
 def test_zero_steps_returns_initial_fields(lb):
