@@ -92,7 +92,9 @@ typedef struct {
  * the artificial diffusivity fene_kappa * lap C, second-order Adams-Bashforth in time
  * (forward Euler for the first step after set_fields).  Runs on the chained and split
  * paths (a lattice tuned to the fused or two-pass path steps on the split path, and
- * lbfd_get_tuning reports it); batches take UPWIND_EULER only. */
+ * lbfd_get_tuning reports it).  Batches run it in the chained batch body; there an
+ * instance's first step after its fields are set is a forward Euler step, as for a single
+ * lattice. */
 #define LBFD_FENE_UPWIND_EULER 0
 #define LBFD_FENE_CHOLESKY_AB2 1
 
@@ -102,8 +104,9 @@ typedef struct {
  * (tau_s = tau_b), the species momenta with tau_M = 1, the other modes with rate 1, and
  * the source is weighted by I - Lambda/2 in moment space (eq. TRANSPORTCOEFF and the text
  * after it).  MRT runs on the chained and split paths (a lattice tuned to the fused or
- * two-pass path steps on the split path, and lbfd_get_tuning reports it); batches take BGK
- * only. */
+ * two-pass path steps on the split path, and lbfd_get_tuning reports it).  Batches run it
+ * in the chained batch body.  All instances of a batch share the collision and FENE-P
+ * options (EINVAL otherwise, and with a non-default option on the fused batch path). */
 #define LBFD_COLLISION_BGK 0
 #define LBFD_COLLISION_MRT 1
 

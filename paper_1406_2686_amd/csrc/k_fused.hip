@@ -1317,8 +1317,10 @@ __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused_batch(
 }
 
 // Chained step for many lattices: the k_fused_batch work table, 64x8 tiles, and each
-// instance's moments carried in mom[cur ^ parity] -> mom[cur ^ parity ^ 1].
-template <int NC>
+// instance's moments carried in mom[cur ^ parity] -> mom[cur ^ parity ^ 1] (and, with the
+// Cholesky integrator, its rate history in ab the same way).  FE and CO as for k_fused3,
+// shared by every instance of the batch.
+template <int NC, int FE, int CO>
 __global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3_batch(
     const BatchInstance* __restrict__ inst, const WorkItem* __restrict__ work, int parity) {
     __shared__ FusedTile<NC, 64, 8, true, true> L;
@@ -1327,8 +1329,8 @@ __global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3_batch(
     const BatchInstance& bi = inst[w.inst];
     const DevParams p = bi.p;
     const int c = bi.cur ^ parity;
-    fused_tile<NC, 64, 8, true, true>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0, w.z0,
-                                      w.z1, bi.mom[c], bi.mom[c ^ 1]);
+    fused_tile<NC, 64, 8, true, true, FE, CO>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0,
+                                              w.z0, w.z1, bi.mom[c], bi.mom[c ^ 1], bi.ab[c], bi.ab[c ^ 1]);
 }
 
 template <int NC, int TX, int TY>
@@ -1401,14 +1403,26 @@ hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, i
     return hipGetLastError();
 }
 
-hipError_t launch_fused3_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int parity,
-                               hipStream_t s) {
+template <int NC, int FE, int CO>
+static void launch_fused3_batch_t(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int parity,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL((k_fused3_batch<NC, FE, CO>), dim3((unsigned)nwork), dim3(NC * 512), 0, s, inst, work, parity);
+}
+
+hipError_t launch_fused3_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int fene,
+                               int collision, int parity, hipStream_t s) {
     if (nwork <= 0) return hipSuccess;
-    const dim3 grid((unsigned)nwork);
-    if (ncomp == 2)
-        hipLaunchKernelGGL((k_fused3_batch<2>), grid, dim3(1024), 0, s, inst, work, parity);
-    else
-        hipLaunchKernelGGL((k_fused3_batch<1>), grid, dim3(512), 0, s, inst, work, parity);
+    const int sel = (ncomp == 2 ? 4 : 0) + (fene == 1 ? 2 : 0) + (collision == 1 ? 1 : 0);
+    switch (sel) {
+        case 0: launch_fused3_batch_t<1, 0, 0>(inst, work, nwork, parity, s); break;
+        case 1: launch_fused3_batch_t<1, 0, 1>(inst, work, nwork, parity, s); break;
+        case 2: launch_fused3_batch_t<1, 1, 0>(inst, work, nwork, parity, s); break;
+        case 3: launch_fused3_batch_t<1, 1, 1>(inst, work, nwork, parity, s); break;
+        case 4: launch_fused3_batch_t<2, 0, 0>(inst, work, nwork, parity, s); break;
+        case 5: launch_fused3_batch_t<2, 0, 1>(inst, work, nwork, parity, s); break;
+        case 6: launch_fused3_batch_t<2, 1, 0>(inst, work, nwork, parity, s); break;
+        default: launch_fused3_batch_t<2, 1, 1>(inst, work, nwork, parity, s); break;
+    }
     return hipGetLastError();
 }
 

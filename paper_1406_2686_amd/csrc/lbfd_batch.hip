@@ -85,6 +85,9 @@ hipError_t upload_tables(lbfd_batch* b) {
         it[i].D[1] = c->Dbuf[1];
         it[i].mom[0] = c->mbuf[0];
         it[i].mom[1] = c->mbuf[1];
+        it[i].ab[0] = c->abuf[0];
+        it[i].ab[1] = c->abuf[1];
+        it[i].p.ab_hist = c->ab_valid ? 1 : 0;
         it[i].flags = c->buf.flags;
         it[i].cur = b->cur[i];
         it[i].pad = 0;
@@ -110,9 +113,21 @@ hipError_t upload_tables(lbfd_batch* b) {
     return e;
 }
 
+// The collision and FENE-P options of the batch: every instance must share them (one
+// kernel instantiation runs them all).  Returns false if they differ.
+bool batch_options(const lbfd_batch* b, int* fene, int* collision) {
+    *fene = b->inst[0]->dp.fene;
+    *collision = b->inst[0]->dp.collision;
+    for (int i = 1; i < b->n; ++i)
+        if (b->inst[i]->dp.fene != *fene || b->inst[i]->dp.collision != *collision) return false;
+    return true;
+}
+
 hipError_t launch_batch(lbfd_batch* b, int parity) {
+    int fene = 0, coll = 0;
+    (void)batch_options(b, &fene, &coll);
     if (b->tune.path == LBFD_PATH_CHAINED)
-        return launch_fused3_batch(b->d_inst, b->d_work, b->nwork, b->ncomp, parity, b->stream);
+        return launch_fused3_batch(b->d_inst, b->d_work, b->nwork, b->ncomp, fene, coll, parity, b->stream);
     return launch_fused_batch(b->d_inst, b->d_work, b->nwork, b->ncomp, b->tune.tile, parity, b->stream);
 }
 
@@ -191,6 +206,7 @@ void advance(lbfd_batch* b, int64_t n) {
         } else if (n > 0) {
             c->mom_valid = false;  // the fused batch step does not carry moments
         }
+        if (n > 0) c->ab_valid = c->dp.fene == LBFD_FENE_CHOLESKY_AB2;  // this step's rate was written
         bind_current(c);
     }
 }
@@ -309,21 +325,38 @@ lbfd_status lbfd_batch_set_active(lbfd_batch* b, const uint8_t* active) {
 
 lbfd_status lbfd_batch_step(lbfd_batch* b, int64_t nsteps) {
     if (!b || nsteps < 0) return LBFD_EINVAL;
-    for (int i = 0; i < b->n; ++i) {
+    for (int i = 0; i < b->n; ++i)
         if (b->active[i] && !b->inst[i]->have_fields) return bfail(b, LBFD_ESTATE, "instance without fields");
-        if (b->inst[i]->dp.collision != LBFD_COLLISION_BGK || b->inst[i]->dp.fene != LBFD_FENE_UPWIND_EULER)
-            return bfail(b, LBFD_EINVAL, "batches take the BGK collision and the upwind-Euler FENE-P step only");
-    }
+    int fene = 0, coll = 0;
+    if (!batch_options(b, &fene, &coll))
+        return bfail(b, LBFD_EINVAL, "the instances of a batch must share the collision and FENE-P options");
+    if ((fene != LBFD_FENE_UPWIND_EULER || coll != LBFD_COLLISION_BGK) && b->tune.path != LBFD_PATH_CHAINED)
+        return bfail(b, LBFD_EINVAL, "the MRT collision and the Cholesky integrator run in the chained batch body");
     (void)hipSetDevice(b->device);
     BCHK(b, ensure_ready(b), "batch tables");
     BCHK(b, align_moments(b), "batch moments");
     int64_t done = 0;
+    if (nsteps > 0 && fene == LBFD_FENE_CHOLESKY_AB2) {
+        // an instance without a rate history takes its first step as forward Euler: one
+        // eager step with the history flags of the instance table as they stand, then the
+        // table with every flag set for the graph replays
+        bool need = false;
+        for (int i = 0; i < b->n; ++i) need |= b->active[i] && !b->inst[i]->ab_valid;
+        if (need) {
+            BCHK(b, upload_tables(b), "batch tables");
+            BCHK(b, launch_batch(b, 0), "batch launch");
+            advance(b, 1);
+            BCHK(b, upload_tables(b), "batch tables");
+            done = 1;
+        }
+    }
+    const int64_t first = done;
     if (b->graph_ok)
         for (; done + 2 <= nsteps; done += 2) BCHK(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
     // remaining steps (or all, without a graph): alternate the parity eagerly
     for (int par = 0; done < nsteps; ++done, par ^= 1) BCHK(b, launch_batch(b, par), "batch launch");
-    advance(b, nsteps);
-    if (nsteps & 1) BCHK(b, upload_tables(b), "batch tables");  // new parity per instance
+    advance(b, nsteps - first);
+    if ((nsteps - first) & 1) BCHK(b, upload_tables(b), "batch tables");  // new parity per instance
     unsigned all = 0;
     for (int i = 0; i < b->n; ++i) {
         if (!b->active[i]) continue;
@@ -415,7 +448,12 @@ lbfd_status lbfd_batch_autotune(lbfd_batch* b, int32_t reps, lbfd_tuning* best, 
     const int zcs[5] = {16, 32, 64, 128, 256};
     Tuning keep = b->tune, win = b->tune;
     float best_ms = 1e30f;
+    int fene = 0, coll = 0;
+    if (!batch_options(b, &fene, &coll))
+        return bfail(b, LBFD_EINVAL, "the instances of a batch must share the collision and FENE-P options");
+    const bool options = fene != LBFD_FENE_UPWIND_EULER || coll != LBFD_COLLISION_BGK;
     for (const auto& sh : shapes) {
+        if (options && sh[0] != LBFD_PATH_CHAINED) continue;  // only the chained body has them
         for (int zc : zcs) {
             b->tune = Tuning{sh[0], sh[1], zc};
             BCHK(b, upload_tables(b), "batch tables");

@@ -69,6 +69,7 @@ struct BatchInstance {
     float* h[2];       // the two population buffers
     float* D[2];       // the two C - I buffers
     float* mom[2];     // the two moments buffers (chained batch step; same parity as h and D)
+    float* ab[2];      // the two FENE-P rate-history buffers (Cholesky integrator; same parity)
     unsigned* flags;   // this instance's fault bits
     int cur;           // buffer index holding time level n when the launch parity is 0
     int pad;
@@ -94,8 +95,9 @@ hipError_t launch_fused3(const DevParams& p, const Buffers& b, const Tuning& t, 
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,
                               int parity, hipStream_t s);
 // chained step over a work table of 64x8 tiles (moments of level n in mom[cur ^ parity])
-hipError_t launch_fused3_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int parity,
-                               hipStream_t s);
+// fene, collision: the options every instance of the batch shares (DevParams::fene, ::collision)
+hipError_t launch_fused3_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int fene,
+                               int collision, int parity, hipStream_t s);
 void fused_tile_shape(int ncomp, int tile, int* tx, int* ty);
 
 // field transfer kernels (k_fields.hip)

@@ -99,6 +99,40 @@ def test_chained_batch_matches_chained_single_lattices_bitwise(lb):
     b.close()
 
 
+@pytest.mark.parametrize("collision,fene", [("mrt", "upwind_euler"), ("bgk", "cholesky_ab2"),
+                                           ("mrt", "cholesky_ab2")])
+def test_batches_with_the_papers_schemes_match_single_lattices_bitwise(lb, collision, fene):
+    """The paper's MRT collision and Cholesky-log integrator in the chained batch body
+    (every instance with the same options) against single chained lattices, bitwise: the
+    first step after the fields are set is forward Euler in both (the batch takes it
+    eagerly, before the graph replays), odd step counts and diagnostics between the
+    calls, and a retired instance whose rate history waits with it."""
+    cases = [dict(w, params=dict(w["params"], collision=collision, fene=fene, kappa=0.01))
+             for w in small_cases()]
+    b = lb.Batch(cases)
+    total = 0
+    for n in (10, 7, 1):
+        b.step(n)
+        total += n
+        b.diagnostics()
+        ref = singles(lb, cases, total, lb.PATH_CHAINED)
+        for i in range(len(cases)):
+            for a, r in zip(b.get_fields(i), ref[i]):
+                assert np.array_equal(a, r), (collision, fene, i, total)
+    b.set_active([True, False, True, True, True])
+    b.step(5)
+    b.set_active([True] * 5)
+    b.step(3)
+    ref = singles(lb, cases, total + 8, lb.PATH_CHAINED)
+    ref1 = singles(lb, [cases[1]], total + 3, lb.PATH_CHAINED)[0]
+    for i in range(len(cases)):
+        for a, r in zip(b.get_fields(i), ref1 if i == 1 else ref[i]):
+            assert np.array_equal(a, r), (collision, fene, i, "after retire")
+    res = b.autotune(reps=1)
+    assert res["path"] == lb.PATH_CHAINED   # the only body with the options
+    b.close()
+
+
 def test_retired_instances_stay_frozen(lb):
     cases = small_cases()[:3]
     b = lb.Batch(cases)

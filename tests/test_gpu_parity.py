@@ -544,9 +544,10 @@ def test_chained_options_agree_bitwise_across_zchunks_and_match_split(lb, fene):
     assert e["u"] < 5e-6 and e["C"] < 1e-6 and e["rho"] < 1e-7
 
 
-def test_mrt_at_unit_tau_agrees_with_bgk_and_batches_refuse_it(lb):
-    """At tau = 1 every MRT rate is 1 and the step is the BGK step (FP32 rounding apart);
-    the batched bodies have no MRT and refuse it."""
+def test_mrt_at_unit_tau_agrees_with_bgk_and_batches_check_options(lb):
+    """At tau = 1 every MRT rate is 1 and the step is the BGK step (FP32 rounding apart).
+    A batch refuses instances whose options differ, and options on the fused batch body,
+    which has none of them."""
     wl = workloads.droplet_shear(nx=40, ny=20, nz=24, R=6.0, G=workloads.G_PHYSICS_1_004,
                                  polymer_phase="A", De=0.5, U=0.01)
     out = []
@@ -560,7 +561,13 @@ def test_mrt_at_unit_tau_agrees_with_bgk_and_batches_refuse_it(lb):
     e = report("mrt-vs-bgk-tau1", out[0], out[1])
     assert e["u"] < 2e-6 and e["rho"] < 1e-7 and e["C"] < 1e-7
     w = dict(wl, params=dict(wl["params"], collision="mrt"))
-    b = lb.Batch([w])
+    b = lb.Batch([w, wl])
+    with pytest.raises(lb.LbfdError) as ei:
+        b.step(2)
+    assert ei.value.status == lb.EINVAL
+    b.close()
+    b = lb.Batch([w, w])
+    b.set_tuning("32x8", 0, path=lb.PATH_FUSED)
     with pytest.raises(lb.LbfdError) as ei:
         b.step(2)
     assert ei.value.status == lb.EINVAL
