@@ -187,7 +187,9 @@ class Oracle:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        # at interpreter exit the module's globals may already be gone: the process is
+        # ending and takes the oracle's memory with it
+        if h and lib is not None:
             lib().orc_destroy(h)
             self._h = None
 
