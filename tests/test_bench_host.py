@@ -1,6 +1,7 @@
-"""Host logic of bench.py (no GPU): the multi-GPU refusal, the guard on recorded traffic
-(kernel sources must hash to the profiled ones; other options get none), and the sweep
-judgement (shape-sensitive cases, fastest path within |dD| <= 0.01)."""
+"""Host logic of bench.py and the sweep driver (no GPU): the multi-GPU refusal, the guard on
+recorded traffic (kernel sources must hash to the profiled ones; other options get none),
+the sweep judgement (shape-sensitive cases, fastest path within |dD| <= 0.01), and the
+per-case steady test over consecutive windows."""
 import hashlib
 import json
 import os
@@ -55,3 +56,58 @@ def test_sweep_judgement():
     # nothing faster qualifies: the plain sweep answers itself
     J2 = bench.sweep_judgement(plain, cold, {"batched_cold": (27.0, cold["D"] + 0.02)})
     assert J2["best"] == (70.0, "plain")
+
+
+class _StubLattice:
+    """Stands in for a lattice in the per-case sweep loop: D(t) follows a prescribed
+    sequence, sampled once per `every` steps."""
+
+    def __init__(self, seq):
+        self.seq, self.k = seq, 0
+
+    def autotune(self, reps=1):
+        return {}
+
+    def step_status(self, n):
+        self.k += 1
+        return 0
+
+    def diagnostics(self):
+        return {"D": self.seq[min(self.k, len(self.seq)) - 1]}
+
+    def close(self):
+        pass
+
+
+class _StubLb:
+    def __init__(self, seqs):
+        self.seqs = list(seqs)
+
+    def from_workload(self, wl):
+        return _StubLattice(self.seqs.pop(0))
+
+
+def test_per_case_steady_test_over_consecutive_windows(monkeypatch):
+    """D(t) with a plateau (a slow extremum of the transient) before it moves on: one window
+    of two samples is met on the plateau, two consecutive windows are not, and both are met
+    once D has settled."""
+    import types
+
+    from paper_1406_2686_amd import surrogate as sg
+
+    torch_stub = types.SimpleNamespace(cuda=types.SimpleNamespace(synchronize=lambda: None))
+    monkeypatch.setitem(sys.modules, "torch", torch_stub)
+    plateau = [0.10, 0.12, 0.13, 0.13, 0.13, 0.15, 0.18, 0.20, 0.20, 0.20, 0.20, 0.20, 0.20]
+    one = sg.solve_plain(_StubLb([plateau]), [None], every=100, window=200, tol=1e-3, max_steps=5000,
+                         autotune=False, windows=1)
+    two = sg.solve_plain(_StubLb([plateau]), [None], every=100, window=200, tol=1e-3, max_steps=5000,
+                         autotune=False, windows=2)
+    # one window: samples 3 and 5 (t = 300, 500) agree -> steady at t = 500, D = 0.13
+    assert one["steady_step"][0] == 500 and one["D"][0] == 0.13
+    # two windows: samples t - 400, t - 200, t all agree only from t = 1200 on
+    assert two["steady_step"][0] == 1200 and two["D"][0] == 0.20
+    # never settling: not steady (-1) after max_steps
+    ramp = [0.01 * k for k in range(1, 80)]
+    r = sg.solve_plain(_StubLb([ramp]), [None], every=100, window=200, tol=1e-3, max_steps=3000,
+                       autotune=False, windows=2)
+    assert r["steady_step"][0] == -1
