@@ -19,7 +19,6 @@ HIPCC_FLAGS = [
     "-shared",
     # packed FP32 instructions are disabled on purpose for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics",
     "-Wno-unused-command-line-argument",
 ]
 
