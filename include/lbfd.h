@@ -173,6 +173,7 @@ lbfd_status lbfd_step(lbfd_ctx* ctx, int64_t nsteps);
 lbfd_status lbfd_step_async(lbfd_ctx* ctx, int64_t nsteps);
 lbfd_status lbfd_get_flags(lbfd_ctx* ctx, uint32_t* flags);
 
+
 /* Macroscopic fields of the current state: rho (ncomp x N), u (3 x N, including the
  * half-force shift of Sec. 2, eq. equilibrium:vel) and C (6 x N).  Any pointer may be
  * NULL.  Synchronises the stream. */
@@ -182,6 +183,18 @@ lbfd_status lbfd_get_fields_box(lbfd_ctx* ctx, int32_t x0, int32_t y0, int32_t z
 
 /* FP64 diagnostics record of the current state.  Synchronises the stream. */
 lbfd_status lbfd_diagnostics(lbfd_ctx* ctx, lbfd_diag* out);
+
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * monitoring loops, harnesses that forbid hipMalloc): the record of lbfd_diagnostics,
+ * computed by the same kernels in the same order (so the two records are identical), with
+ * the reduction's partial records kept in a static per-device array of 164,000 bytes (at
+ * most 1024 stage-1 records of 20 FP64 values plus the final record) instead of the
+ * context's buffer.  Calls no allocating routine.  The array is shared by every call on
+ * one GPU: calls that overlap on one GPU (different streams or threads) race and must be
+ * serialised by the caller.  EINVAL if the reduction would need more partial records
+ * than the array holds (not reachable for valid grids: the first stage is capped at 1024
+ * workgroups), ESTATE before set_fields, EDEVICE on a HIP error.  Synchronises the stream. */
+lbfd_status lbfd_diagnostics_noalloc(lbfd_ctx* ctx, lbfd_diag* out);
 
 /* Raw checkpoint of the device state (FP32 populations, C - I and the moments delta rho, j
  * of the current level, step counter, flags): lbfd_checkpoint_bytes gives the size; get

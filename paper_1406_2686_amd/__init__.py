@@ -107,6 +107,7 @@ _sig("lbfd_get_flags", [_P, ctypes.POINTER(ctypes.c_uint32)])
 _sig("lbfd_get_fields", [_P, _D, _D, _D])
 _sig("lbfd_get_fields_box", [_P, _I32, _I32, _I32, _I32, _I32, _I32, _D, _D, _D])
 _sig("lbfd_diagnostics", [_P, ctypes.POINTER(Diag)])
+_sig("lbfd_diagnostics_noalloc", [_P, ctypes.POINTER(Diag)])
 _sig("lbfd_checkpoint_bytes", [_P, ctypes.POINTER(ctypes.c_uint64)])
 _sig("lbfd_get_state", [_P, _P, ctypes.c_uint64])
 _sig("lbfd_set_state", [_P, _P, ctypes.c_uint64])
@@ -322,6 +323,13 @@ class Lattice:
     def diagnostics(self) -> dict:
         d = Diag()
         self._check(_lib.lbfd_diagnostics(self._h, ctypes.byref(d)))
+        return d.to_dict()
+
+    def diagnostics_noalloc(self) -> dict:
+        """The record of diagnostics(), reduced through the library's static per-device
+        scratch instead of the lattice's buffer (lbfd_diagnostics_noalloc)."""
+        d = Diag()
+        self._check(_lib.lbfd_diagnostics_noalloc(self._h, ctypes.byref(d)))
         return d.to_dict()
 
     def get_state(self) -> bytes:

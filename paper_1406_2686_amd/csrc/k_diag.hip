@@ -19,7 +19,6 @@
 namespace lbfd {
 
 constexpr int kDB = 256;
-constexpr int kMaxDiagBlocks = 1024;
 
 int64_t diag_blocks(int64_t N) {
     int64_t b = (N + kDB - 1) / kDB;
@@ -139,13 +138,19 @@ __global__ __launch_bounds__(kDB) void k_diag_stage2(const double* __restrict__ 
     block_reduce_store(acc, out);
 }
 
-hipError_t launch_diag(const DevParams& p, const Buffers& b, hipStream_t s) {
+hipError_t launch_diag_into(const DevParams& p, const Buffers& b, double* part, double* out, hipStream_t s) {
+    // stage 1 writes every one of its nb records and stage 2 reads exactly those, so the
+    // partials need no clearing between calls
     const int nb = (int)diag_blocks(p.N);
-    hipLaunchKernelGGL(k_diag_stage1, dim3(nb), dim3(kDB), 0, s, p, b.mom, b.uF, b.D, b.red);
+    hipLaunchKernelGGL(k_diag_stage1, dim3(nb), dim3(kDB), 0, s, p, b.mom, b.uF, b.D, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diag_stage2, dim3(1), dim3(kDB), 0, s, b.red, nb, b.red_out);
+    hipLaunchKernelGGL(k_diag_stage2, dim3(1), dim3(kDB), 0, s, part, nb, out);
     return hipGetLastError();
+}
+
+hipError_t launch_diag(const DevParams& p, const Buffers& b, hipStream_t s) {
+    return launch_diag_into(p, b, b.red, b.red_out, s);
 }
 
 }  // namespace lbfd

@@ -240,6 +240,39 @@ hipError_t enqueue_steps(lbfd_ctx* c, int64_t n) {
     return hipSuccess;
 }
 
+void fill_diag(const lbfd_ctx* c, const double* r, lbfd_diag* out) {
+    memset(out, 0, sizeof(*out));
+    out->mass[0] = r[0];
+    out->mass[1] = r[1];
+    for (int d = 0; d < 3; ++d) out->momentum[d] = r[2 + d];
+    const double W = r[5];
+    out->W = W;
+    if (W > 0.0) {
+        const double xc = r[6] / W, yc = r[7] / W, zc = r[8] / W;
+        out->centroid[0] = xc;
+        out->centroid[1] = yc;
+        out->centroid[2] = zc;
+        const double cen[3] = {xc, yc, zc};
+        const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+        for (int k = 0; k < 6; ++k) out->M[k] = r[9 + k] / W - cen[ii[k]] * cen[jj[k]];
+        // principal axes of the x-y block (Sec. 4.1: axes a, b in the shear plane)
+        const double tr = out->M[0] + out->M[1], df = out->M[0] - out->M[1];
+        const double rad = sqrt(0.25 * df * df + out->M[3] * out->M[3]);
+        const double l1 = 0.5 * tr + rad;
+        double l2 = 0.5 * tr - rad;
+        if (l2 < 0.0) l2 = 0.0;
+        const double a = sqrt(l1), b = sqrt(l2);
+        out->D = (a + b) > 0.0 ? (a - b) / (a + b) : 0.0;
+        out->theta_deg = rad > 0.0 ? 0.5 * atan2(2.0 * out->M[3], df) * (180.0 / M_PI) : 0.0;
+    }
+    out->min_L2_minus_trC = r[15];
+    out->min_minor = r[16];
+    out->max_u = r[17];
+    out->flags = c->flags_seen;
+    out->step = c->steps;
+    out->poly_trace_excess = r[19] > 0.0 ? r[18] / r[19] : 0.0;
+}
+
 hipError_t read_flags(lbfd_ctx* c, unsigned* out) {
     unsigned f = 0;
     hipError_t e = hipMemcpyAsync(&f, c->buf.flags, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream);
@@ -503,36 +536,7 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
     unsigned f = 0;
     HIPCHK(c, read_flags(c, &f), "read flags");
     c->flags_seen |= f;
-    memset(out, 0, sizeof(*out));
-    out->mass[0] = r[0];
-    out->mass[1] = r[1];
-    for (int d = 0; d < 3; ++d) out->momentum[d] = r[2 + d];
-    const double W = r[5];
-    out->W = W;
-    if (W > 0.0) {
-        const double xc = r[6] / W, yc = r[7] / W, zc = r[8] / W;
-        out->centroid[0] = xc;
-        out->centroid[1] = yc;
-        out->centroid[2] = zc;
-        const double cen[3] = {xc, yc, zc};
-        const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
-        for (int k = 0; k < 6; ++k) out->M[k] = r[9 + k] / W - cen[ii[k]] * cen[jj[k]];
-        // principal axes of the x-y block (Sec. 4.1: axes a, b in the shear plane)
-        const double tr = out->M[0] + out->M[1], df = out->M[0] - out->M[1];
-        const double rad = sqrt(0.25 * df * df + out->M[3] * out->M[3]);
-        const double l1 = 0.5 * tr + rad;
-        double l2 = 0.5 * tr - rad;
-        if (l2 < 0.0) l2 = 0.0;
-        const double a = sqrt(l1), b = sqrt(l2);
-        out->D = (a + b) > 0.0 ? (a - b) / (a + b) : 0.0;
-        out->theta_deg = rad > 0.0 ? 0.5 * atan2(2.0 * out->M[3], df) * (180.0 / M_PI) : 0.0;
-    }
-    out->min_L2_minus_trC = r[15];
-    out->min_minor = r[16];
-    out->max_u = r[17];
-    out->flags = c->flags_seen;
-    out->step = c->steps;
-    out->poly_trace_excess = r[19] > 0.0 ? r[18] / r[19] : 0.0;
+    fill_diag(c, r, out);
     return LBFD_OK;
 }
 

@@ -43,5 +43,8 @@ hipError_t enqueue_steps(lbfd_ctx* c, int64_t n);
 bool path_supports(const lbfd_ctx* c, int path);
 int step_path(const lbfd_ctx* c);
 hipError_t read_flags(lbfd_ctx* c, unsigned* out);
+// the public record from the kDiagVals FP64 sums of the diagnostics kernels (D and theta
+// from the x-y block of the central second moments)
+void fill_diag(const lbfd_ctx* c, const double* r, lbfd_diag* out);
 void bind_current(lbfd_ctx* c);
 }  // namespace lbfd

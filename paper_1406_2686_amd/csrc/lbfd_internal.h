@@ -61,7 +61,8 @@ struct Tuning {
     int zchunk;
 };
 
-constexpr int kDiagVals = 20;  // per-block FP64 reduction record length
+constexpr int kDiagVals = 20;        // per-block FP64 reduction record length
+constexpr int kMaxDiagBlocks = 1024;  // stage-1 workgroups of the diagnostics (grid-stride beyond)
 
 // One lattice of a batch, as the batched step kernel sees it (device memory).
 struct BatchInstance {
@@ -106,6 +107,8 @@ hipError_t launch_fields_box(const DevParams& p, const Buffers& b, const Box& bo
 
 // diagnostics (k_diag.hip): writes kDiagVals doubles to b.red_out
 hipError_t launch_diag(const DevParams& p, const Buffers& b, hipStream_t s);
+// the same with the diag_blocks(N) stage-1 records in `part` and the final record in `out`
+hipError_t launch_diag_into(const DevParams& p, const Buffers& b, double* part, double* out, hipStream_t s);
 int64_t diag_blocks(int64_t N);
 
 }  // namespace lbfd
