@@ -173,6 +173,19 @@ lbfd_status lbfd_step(lbfd_ctx* ctx, int64_t nsteps);
 lbfd_status lbfd_step_async(lbfd_ctx* ctx, int64_t nsteps);
 lbfd_status lbfd_get_flags(lbfd_ctx* ctx, uint32_t* flags);
 
+/* Prescribed-velocity ("kinematic") FENE-P stepping for the homogeneous rheology benchmarks
+ * of Sec. 3 (steady shear 3.1, uniaxial elongation 3.2, small-amplitude oscillatory shear
+ * 3.3, inception and cessation 3.4), where the flow is imposed and the polymer does not act
+ * back on it: the velocity is held at the host field u (3 x N, FP64, converted to FP32) and
+ * only the FENE-P update of C (eq. FENE with the lattice's fene_scheme, fene_kappa, L2 and
+ * tau_p; velocity gradients by central differences with wall ghosts 2 u_w - u from
+ * lbfd_set_walls; C ghosts by linear extrapolation) runs nsteps >= 0 times.  The
+ * lattice-Boltzmann populations are not advanced, the step counter does not move, and
+ * fields read afterwards report the velocity of the populations, not u.  The Cholesky-log
+ * integrator carries its Adams-Bashforth history across calls (forward Euler first after
+ * set_fields).  Returns the first fault as lbfd_step; EINVAL for a non-finite u, ESTATE
+ * before set_fields. */
+lbfd_status lbfd_fenep_kinematic(lbfd_ctx* ctx, const double* u, int64_t nsteps);
 
 /* Macroscopic fields of the current state: rho (ncomp x N), u (3 x N, including the
  * half-force shift of Sec. 2, eq. equilibrium:vel) and C (6 x N).  Any pointer may be

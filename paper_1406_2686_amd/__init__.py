@@ -104,6 +104,7 @@ _sig("lbfd_reset_counters", [_P])
 _sig("lbfd_step", [_P, _I64])
 _sig("lbfd_step_async", [_P, _I64])
 _sig("lbfd_get_flags", [_P, ctypes.POINTER(ctypes.c_uint32)])
+_sig("lbfd_fenep_kinematic", [_P, _D, _I64])
 _sig("lbfd_get_fields", [_P, _D, _D, _D])
 _sig("lbfd_get_fields_box", [_P, _I32, _I32, _I32, _I32, _I32, _I32, _D, _D, _D])
 _sig("lbfd_diagnostics", [_P, ctypes.POINTER(Diag)])
@@ -277,6 +278,12 @@ class Lattice:
 
     def step_async(self, n: int):
         self._check(_lib.lbfd_step_async(self._h, int(n)))
+
+    def fenep_kinematic(self, u, n: int):
+        """Advance C by n FENE-P steps under the prescribed velocity u (3, N), the
+        lattice-Boltzmann part switched off (lbfd_fenep_kinematic)."""
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, self.N)
+        self._check(_lib.lbfd_fenep_kinematic(self._h, _dp(u), int(n)))
 
     def flags(self) -> int:
         f = ctypes.c_uint32(0)

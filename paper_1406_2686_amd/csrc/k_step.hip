@@ -199,6 +199,140 @@ __global__ __launch_bounds__(kBlock) void k_forces(DevParams p, const float* __r
     if (bad) atomicOr(flags, bad);
 }
 
+// FENE-P update of C = I + D at node n (Sec. 2, eq. FENE): velocity gradient G_ij = d_i u_j by
+// central differences of the velocity field uF[0..2] (wall ghosts 2 u_w - u), first-order
+// upwind advection and forward Euler (FENE = 0), or the paper's integrator (FENE = 1:
+// central advection, artificial diffusivity, the rate taken through the Cholesky factor of
+// f C with Adams-Bashforth 2; history in ab / abn).  Ghost C across a wall by linear
+// extrapolation.  Writes the new D to dnew (and the rate history to abn) and returns the
+// fault bits raised on the way (2: tr C reached L^2, 4: the Cholesky factor failed).
+template <int FENE>
+__device__ __forceinline__ unsigned fenep_node(const DevParams& p, int64_t n, int x, int y, int z, int xp, int xm,
+                                               int zp, int zm, const float u[3], const float* __restrict__ uF,
+                                               const float* __restrict__ D, const float* __restrict__ ab,
+                                               float* __restrict__ abn, float dnew[6]) {
+    const int64_t N = p.N;
+    const int nx = p.nx, ny = p.ny;
+    float d0[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d0[k] = D[k * N + n];
+    float Gm[3][3];
+    float adv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        // neighbours along axis i
+        int64_t mp, mm;
+        float up[3], um[3];
+        if (i == 0) {
+            mp = ((int64_t)z * ny + y) * nx + xp;
+            mm = ((int64_t)z * ny + y) * nx + xm;
+        } else if (i == 2) {
+            mp = ((int64_t)zp * ny + y) * nx + x;
+            mm = ((int64_t)zm * ny + y) * nx + x;
+        } else {
+            // at a wall the ghost replaces the neighbour; keep the index in bounds anyway
+            mp = y == ny - 1 ? n : n + nx;
+            mm = y == 0 ? n : n - nx;
+        }
+        const bool top = (i == 1) && (y == ny - 1);
+        const bool bot = (i == 1) && (y == 0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            up[d] = top ? 2.0f * p.ut[d] - u[d] : uF[d * N + mp];
+            um[d] = bot ? 2.0f * p.ub[d] - u[d] : uF[d * N + mm];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Gm[i][d] = 0.5f * (up[d] - um[d]);
+        if constexpr (FENE == 1) {
+            // second-order central difference and the artificial diffusivity (ghosts at
+            // the walls by linear extrapolation)
+            float dpl[6], dmi[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                dpl[k] = top ? 2.0f * d0[k] - D[k * N + n - nx] : D[k * N + mp];
+                dmi[k] = bot ? 2.0f * d0[k] - D[k * N + n + nx] : D[k * N + mm];
+                adv[k] += u[i] * (0.5f * (dpl[k] - dmi[k])) - p.kappa * (dpl[k] - 2.0f * d0[k] + dmi[k]);
+            }
+            continue;
+        }
+        // first-order upwind difference of D along i
+        float dn[6];
+        if (u[i] >= 0.0f) {
+            if (bot) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = 2.0f * d0[k] - D[k * N + n + nx];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = D[k * N + mm];
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) adv[k] += u[i] * (d0[k] - dn[k]);
+        } else {
+            if (top) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = 2.0f * d0[k] - D[k * N + n - nx];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dn[k] = D[k * N + mp];
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) adv[k] += u[i] * (dn[k] - d0[k]);
+        }
+    }
+    unsigned bad = 0u;
+    const float trd = d0[0] + d0[1] + d0[2];
+    const float den = p.L2m3 - trd;
+    if (!(den > 0.0f)) bad |= 2u;
+    const float inv = 1.0f / den;
+    const float f = p.L2m3 * inv;
+    const float fm1 = trd * inv;
+    float rate[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            const int kk = sidx(a, b);
+            // (G^T C + C G)_ab with C = I + D
+            float st = Gm[b][a] + Gm[a][b];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) st += Gm[k][a] * d0[sidx(k, b)] + d0[sidx(a, k)] * Gm[k][b];
+            const float relax = (f * d0[kk] + (a == b ? fm1 : 0.0f)) * p.inv_tau_p;
+            rate[kk] = -adv[kk] + st - relax;
+            dnew[kk] = d0[kk] + rate[kk];
+        }
+    }
+    if (FENE == 1 && !(bad & 2u)) {
+        // the paper's integrator: the same rate, taken through the Cholesky factor of f C
+        float yp[6], dn6[6], yd[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) yp[k] = p.ab_hist ? ab[k * N + n] : 0.0f;
+        if (cholesky_ab2_step(p.L2, p.L2m3, d0, rate, yp, p.ab_hist != 0, dn6, yd)) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                dnew[k] = dn6[k];
+                abn[k * N + n] = yd[k];
+            }
+        } else {
+            bad |= 4u;
+        }
+    }
+    return bad;
+}
+
+// Fault bits of a node's new state (S11): 1 non-finite (`check` sums every new value of the
+// node), 2 tr C >= L^2, 4 a leading principal minor of C = I + dnew not positive.
+__device__ __forceinline__ unsigned new_state_faults(const DevParams& p, const float dnew[6], float check) {
+    unsigned bad = 0u;
+    if (!isfinite(check)) bad |= 1u;
+    const float c0 = 1.0f + dnew[0], c1 = 1.0f + dnew[1], c2 = 1.0f + dnew[2];
+    if (!(c0 + c1 + c2 < p.L2)) bad |= 2u;
+    const float m2 = c0 * c1 - dnew[3] * dnew[3];
+    const float m3 = c0 * (c1 * c2 - dnew[5] * dnew[5]) - dnew[3] * (dnew[3] * c2 - dnew[5] * dnew[4]) +
+                     dnew[4] * (dnew[3] * dnew[5] - c1 * dnew[4]);
+    if (!(c0 > 0.0f && m2 > 0.0f && m3 > 0.0f)) bad |= 4u;
+    return bad;
+}
+
 // COLL: 0 BGK, 1 MRT; FENE: 0 upwind/Euler, 1 the Cholesky-log AB2 integrator.  Each option
 // pair is its own instantiation, so the default BGK body keeps the register budget of the
 // plain scheme.
@@ -355,122 +489,47 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
     }
 
     // ---- FENE-P step on C = I + D ----
-    float d0[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) d0[k] = D[k * N + n];
-    float Gm[3][3];
-    float adv[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        // neighbours along axis i
-        int64_t mp, mm;
-        float up[3], um[3];
-        if (i == 0) {
-            mp = ((int64_t)z * ny + y) * nx + xp;
-            mm = ((int64_t)z * ny + y) * nx + xm;
-        } else if (i == 2) {
-            mp = ((int64_t)zp * ny + y) * nx + x;
-            mm = ((int64_t)zm * ny + y) * nx + x;
-        } else {
-            // at a wall the ghost replaces the neighbour; keep the index in bounds anyway
-            mp = y == ny - 1 ? n : n + nx;
-            mm = y == 0 ? n : n - nx;
-        }
-        const bool top = (i == 1) && (y == ny - 1);
-        const bool bot = (i == 1) && (y == 0);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            up[d] = top ? 2.0f * p.ut[d] - u[d] : uF[d * N + mp];
-            um[d] = bot ? 2.0f * p.ub[d] - u[d] : uF[d * N + mm];
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) Gm[i][d] = 0.5f * (up[d] - um[d]);
-        if constexpr (FENE == 1) {
-            // second-order central difference and the artificial diffusivity (ghosts at
-            // the walls by linear extrapolation)
-            float dpl[6], dmi[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                dpl[k] = top ? 2.0f * d0[k] - D[k * N + n - nx] : D[k * N + mp];
-                dmi[k] = bot ? 2.0f * d0[k] - D[k * N + n + nx] : D[k * N + mm];
-                adv[k] += u[i] * (0.5f * (dpl[k] - dmi[k])) - p.kappa * (dpl[k] - 2.0f * d0[k] + dmi[k]);
-            }
-            continue;
-        }
-        // first-order upwind difference of D along i
-        float dn[6];
-        if (u[i] >= 0.0f) {
-            if (bot) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) dn[k] = 2.0f * d0[k] - D[k * N + n + nx];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) dn[k] = D[k * N + mm];
-            }
-#pragma unroll
-            for (int k = 0; k < 6; ++k) adv[k] += u[i] * (d0[k] - dn[k]);
-        } else {
-            if (top) {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) dn[k] = 2.0f * d0[k] - D[k * N + n - nx];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 6; ++k) dn[k] = D[k * N + mp];
-            }
-#pragma unroll
-            for (int k = 0; k < 6; ++k) adv[k] += u[i] * (dn[k] - d0[k]);
-        }
-    }
-    unsigned bad = 0u;
-    const float trd = d0[0] + d0[1] + d0[2];
-    const float den = p.L2m3 - trd;
-    if (!(den > 0.0f)) bad |= 2u;
-    const float inv = 1.0f / den;
-    const float f = p.L2m3 * inv;
-    const float fm1 = trd * inv;
-    float dnew[6], rate[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int b = a; b < 3; ++b) {
-            const int kk = sidx(a, b);
-            // (G^T C + C G)_ab with C = I + D
-            float st = Gm[b][a] + Gm[a][b];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) st += Gm[k][a] * d0[sidx(k, b)] + d0[sidx(a, k)] * Gm[k][b];
-            const float relax = (f * d0[kk] + (a == b ? fm1 : 0.0f)) * p.inv_tau_p;
-            rate[kk] = -adv[kk] + st - relax;
-            dnew[kk] = d0[kk] + rate[kk];
-        }
-    }
-    if (FENE == 1 && !(bad & 2u)) {
-        // the paper's integrator: the same rate, taken through the Cholesky factor of f C
-        float yp[6], dn6[6], yd[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) yp[k] = p.ab_hist ? ab[k * N + n] : 0.0f;
-        if (cholesky_ab2_step(p.L2, p.L2m3, d0, rate, yp, p.ab_hist != 0, dn6, yd)) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                dnew[k] = dn6[k];
-                abn[k * N + n] = yd[k];
-            }
-        } else {
-            bad |= 4u;
-        }
-    }
+    float dnew[6];
+    unsigned bad = fenep_node<FENE>(p, n, x, y, z, xp, xm, zp, zm, u, uF, D, ab, abn, dnew);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         Dn[k * N + n] = dnew[k];
         check += dnew[k];
     }
-    // fault checks on the new state: non-finite, extensibility, leading minors of C
-    if (!isfinite(check)) bad |= 1u;
-    const float c0 = 1.0f + dnew[0], c1 = 1.0f + dnew[1], c2 = 1.0f + dnew[2];
-    if (!(c0 + c1 + c2 < p.L2)) bad |= 2u;
-    const float m2 = c0 * c1 - dnew[3] * dnew[3];
-    const float m3 = c0 * (c1 * c2 - dnew[5] * dnew[5]) - dnew[3] * (dnew[3] * c2 - dnew[5] * dnew[4]) +
-                     dnew[4] * (dnew[3] * dnew[5] - c1 * dnew[4]);
-    if (!(c0 > 0.0f && m2 > 0.0f && m3 > 0.0f)) bad |= 4u;
+    bad |= new_state_faults(p, dnew, check);
+    if (bad) atomicOr(flags, bad);
+}
+
+// Prescribed-velocity ("kinematic") FENE-P step: the lattice-Boltzmann part is not run; the
+// velocity field uF[0..2] is given and held fixed, and only the FENE-P update above advances
+// C (the homogeneous benchmarks of Sec. 3 prescribe the flow and switch the feedback off).
+template <int FENE>
+__global__ __launch_bounds__(kBlock) void k_fenep_kinematic(DevParams p, const float* __restrict__ uF,
+                                                            const float* __restrict__ D,
+                                                            float* __restrict__ Dn,
+                                                            const float* __restrict__ ab,
+                                                            float* __restrict__ abn,
+                                                            unsigned* __restrict__ flags) {
+    const int64_t n = node_id();
+    if (n >= p.N) return;
+    const int64_t N = p.N;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int x = (int)(n % nx);
+    const int64_t r = n / nx;
+    const int y = (int)(r % ny);
+    const int z = (int)(r / ny);
+    const float u[3] = {uF[n], uF[N + n], uF[2 * N + n]};
+    const int xp = wrap1(x + 1, nx), xm = wrap1(x - 1, nx);
+    const int zp = wrap1(z + 1, nz), zm = wrap1(z - 1, nz);
+    float dnew[6];
+    unsigned bad = fenep_node<FENE>(p, n, x, y, z, xp, xm, zp, zm, u, uF, D, ab, abn, dnew);
+    float check = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        Dn[k * N + n] = dnew[k];
+        check += dnew[k];
+    }
+    bad |= new_state_faults(p, dnew, check);
     if (bad) atomicOr(flags, bad);
 }
 
@@ -497,6 +556,12 @@ hipError_t launch_collide(const DevParams& p, const Buffers& b, hipStream_t s) {
                                     : (p.fene == 1 ? k_collide<0, 1> : k_collide<0, 0>);
     hipLaunchKernelGGL(k, grid_for(p.N), dim3(kBlock), 0, s, p, b.h, b.hn, b.D, b.Dn, b.uF, b.ab, b.ab_next,
                        b.flags);
+    return hipGetLastError();
+}
+hipError_t launch_fenep_kinematic(const DevParams& p, const float* uF, const float* D, float* Dn, const float* ab,
+                                  float* abn, unsigned* flags, hipStream_t s) {
+    const auto k = p.fene == 1 ? k_fenep_kinematic<1> : k_fenep_kinematic<0>;
+    hipLaunchKernelGGL(k, grid_for(p.N), dim3(kBlock), 0, s, p, uF, D, Dn, ab, abn, flags);
     return hipGetLastError();
 }
 hipError_t launch_set_flags(const Buffers& b, unsigned v, hipStream_t s) {

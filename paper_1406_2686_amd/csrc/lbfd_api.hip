@@ -478,6 +478,52 @@ lbfd_status lbfd_step(lbfd_ctx* c, int64_t nsteps) {
     return LBFD_OK;
 }
 
+lbfd_status lbfd_fenep_kinematic(lbfd_ctx* c, const double* u, int64_t nsteps) {
+    if (!c || !u || nsteps < 0) return LBFD_EINVAL;
+    if (!c->have_fields) return fail(c, LBFD_ESTATE, "kinematic steps before set_fields");
+    (void)hipSetDevice(c->device);
+    const int64_t N = c->dp.N;
+    std::vector<float> uf((size_t)3 * N);
+    for (int64_t i = 0; i < 3 * N; ++i) {
+        if (!is_fin(u[i])) return fail(c, LBFD_EINVAL, "non-finite velocity");
+        uf[(size_t)i] = (float)u[i];
+    }
+    // the prescribed velocity takes the place of the half-force velocity of the side fields
+    HIPCHK(c, hipMemcpyAsync(c->buf.uF, uf.data(), uf.size() * 4, hipMemcpyHostToDevice, c->stream),
+           "velocity upload");
+    unsigned before = 0;
+    HIPCHK(c, read_flags(c, &before), "read flags");  // synchronises: the upload has left uf
+    c->flags_seen |= before;
+    HIPCHK(c, launch_clear_flags(c->buf, c->stream), "clear flags");
+    // C - I and the rate history alternate between their two buffers; the populations and
+    // the buffer index of the lattice state are left as they are
+    float* Din = c->Dbuf[c->cur];
+    float* Dout = c->Dbuf[1 - c->cur];
+    float* ain = c->abuf[c->cur];
+    float* aout = c->abuf[1 - c->cur];
+    for (int64_t t = 0; t < nsteps; ++t) {
+        c->dp.ab_hist = c->ab_valid ? 1 : 0;
+        HIPCHK(c, launch_fenep_kinematic(c->dp, c->buf.uF, Din, Dout, ain, aout, c->buf.flags, c->stream),
+               "kinematic step launch");
+        std::swap(Din, Dout);
+        std::swap(ain, aout);
+        c->ab_valid = c->dp.fene == LBFD_FENE_CHOLESKY_AB2;
+    }
+    if (Din != c->Dbuf[c->cur]) {
+        HIPCHK(c, hipMemcpyAsync(c->Dbuf[c->cur], Din, (size_t)6 * N * 4, hipMemcpyDeviceToDevice, c->stream),
+               "C copy");
+        if (c->ab_valid)
+            HIPCHK(c, hipMemcpyAsync(c->abuf[c->cur], ain, (size_t)6 * N * 4, hipMemcpyDeviceToDevice, c->stream),
+                   "history copy");
+    }
+    unsigned f = 0;
+    HIPCHK(c, read_flags(c, &f), "read flags");
+    c->flags_seen |= f;
+    lbfd_status st = flags_status(f);
+    if (st != LBFD_OK) return fail(c, st, "fault flagged during kinematic steps");
+    return LBFD_OK;
+}
+
 lbfd_status lbfd_get_flags(lbfd_ctx* c, uint32_t* flags) {
     if (!c || !flags) return LBFD_EINVAL;
     (void)hipSetDevice(c->device);

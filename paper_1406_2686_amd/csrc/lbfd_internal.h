@@ -86,6 +86,10 @@ hipError_t launch_moments(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_forces(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_collide(const DevParams& p, const Buffers& b, hipStream_t s);
 hipError_t launch_clear_flags(const Buffers& b, hipStream_t s);
+// prescribed-velocity FENE-P step: D -> Dn (and the rate history ab -> abn) with the velocity
+// field uF[0..2] held fixed; no lattice-Boltzmann part
+hipError_t launch_fenep_kinematic(const DevParams& p, const float* uF, const float* D, float* Dn, const float* ab,
+                                  float* abn, unsigned* flags, hipStream_t s);
 hipError_t launch_set_flags(const Buffers& b, unsigned v, hipStream_t s);
 // the fused single-pass step (k_fused.hip)
 hipError_t launch_fused(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);

@@ -217,3 +217,44 @@ def test_run_to_steady_retires_converged_instances(lb):
     with pytest.raises(lb.LbfdError):
         b.run_to_steady(every=10, window=20, tol=1e-6, max_steps=20, windows=-1)
     b.close()
+
+
+@pytest.mark.parametrize("scheme", ["default", "paper"])
+def test_batch_instances_match_the_oracle(lb, scheme):
+    """Each instance of one batch of three uneven lattices (one ragged in every direction,
+    one with a viscosity ratio, one with a narrow wall gap) against the FP64 oracle run on
+    the same seeded inputs: fields to the 1e-5 relative-L2 bar of the single-lattice tests
+    and every diagnostics field.  `paper` runs the paper's scheme throughout (MRT
+    collision, stress in the equilibrium, Cholesky-log integrator with artificial
+    diffusivity) in the chained batch body; `default` the default schemes."""
+    import oracle
+    from parity_helpers import I6, check_diag, grid_shape, rel
+
+    G = workloads.G_PHYSICS_1_004
+    cases = [
+        workloads.droplet_shear(nx=40, ny=16, nz=24, R=5.0, G=G, polymer_phase="A", De=0.5, U=0.01),
+        workloads.droplet_shear(nx=37, ny=21, nz=13, R=4.0, G=G, polymer_phase="B", L2=400.0, De=1.0,
+                                U=0.005, tau_A=1.3),
+        workloads.droplet_shear(nx=72, ny=12, nz=30, R=4.0, G=G, polymer_phase="A", De=1.0, U=0.015,
+                                tau_A=0.8),
+    ]
+    if scheme == "paper":
+        cases = [dict(w, params=dict(w["params"], collision="mrt", fene="cholesky_ab2", coupling="stress",
+                                     kappa=0.01)) for w in cases]
+    steps = 300
+    b = lb.Batch(cases)
+    assert b.get_tuning()["path"] == lb.PATH_CHAINED
+    b.step(steps)
+    dgs = b.diagnostics()
+    got = [b.get_fields(i) for i in range(len(cases))]
+    b.close()
+    for i, wl in enumerate(cases):
+        o = oracle.from_workload(wl)
+        assert o.step(steps) == 0
+        r = o.get_fields()
+        g = got[i]
+        e = {"u": rel(g[1], r[1]), "C": rel(g[2], r[2]), "C-I": rel(g[2] - I6, r[2] - I6),
+             "rho": rel(g[0], r[0])}
+        print(f"batch-{scheme}-{i}", " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+        assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5, (i, e)
+        check_diag(dgs[i], o.diagnostics(), f"batch-{scheme}-{i}", g, r, grid_shape(wl), wl["params"])

@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import workloads
+from parity_helpers import check_diag, grid_shape
 
 pytestmark = pytest.mark.gpu
 
@@ -74,6 +75,7 @@ def test_droplet_128x64x128_full_grid(lb, variant):
     for k in ("mass_A", "mass_B"):
         assert abs(dg[k] - do[k]) < 1e-6 * do[k]
     assert abs(dg["D"] - do["D"]) < 1e-5 and abs(dg["xc"] - do["xc"]) < 1e-6 * do["xc"]
+    check_diag(dg, do, f"cfg1-{variant}", g, r, grid_shape(wl), wl["params"])
     # polymer-phase mean of tr C - 3: the weight f+-(phi) has slope up to 1/(2 Delta) = 5 in
     # phi, so FP32 rounding of phi at interface nodes is amplified five-fold
     assert abs(dg["poly_trace_excess"] - do["poly_trace_excess"]) < 1e-4 * max(1e-3, abs(do["poly_trace_excess"]))
@@ -100,6 +102,7 @@ def test_droplet_long_runs(lb, case):
     e = report(f"long-{case}", g, r)
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
     assert abs(dg["D"] - do["D"]) < 1e-5
+    check_diag(dg, do, f"long-{case}", g, r, grid_shape(wl), wl["params"])
 
 
 @pytest.mark.parametrize("scheme", ["default", "paper"])
@@ -397,6 +400,7 @@ def test_chained_step_matches_oracle(lb, case):
     e = report(f"chained-{case}", g, r)
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
     assert abs(dg["D"] - do["D"]) < 1e-5
+    check_diag(dg, do, f"chained-{case}", g, r, grid_shape(wl), wl["params"])
 
 
 def test_chained_step_restarts_and_diagnostics_bitwise(lb):
