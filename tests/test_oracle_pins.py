@@ -394,3 +394,143 @@ def test_stress_coupling_first_step_closed_form(tau):
     o = oracle.from_workload(wl)
     _, Fp, _ = o.get_forces()
     assert np.allclose(Fp[0], eta_p / tau_p * a * np.sin(k) * np.cos(k * Z), rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("phi", [-0.05, 0.05, 0.3])
+def test_local_relaxation_time_from_shear_wave_decay(phi):
+    """S7 (Sec. 2, eq. smoothingvisco, read as an interpolation of tau): a uniform miscible
+    mixture (G = 0) at order parameter phi relaxes with tau = tau_B + (tau_A - tau_B) f+(phi),
+    f+ = (1 + tanh(phi/Delta))/2, so a small shear wave u_x = a sin(k z) decays at the BGK
+    kinematic viscosity nu = c_s^2 (tau - 1/2) (the transport coefficient of
+    eq. TRANSPORTCOEFF at unit rates).  tau_A = 1.4 and tau_B = 0.7 give viscosities 60 %
+    apart at phi = +-0.05, so the phase that receives tau_A, the tanh form and its width
+    are each fixed; lattice corrections at k = 2 pi/64 stay below 0.3 %.  The wave is read
+    at the centre row of a channel wide enough that the wall layers do not reach it."""
+    nx, ny, nz = 1, 96, 64
+    N = nx * ny * nz
+    X, Y, Z = coords(nx, ny, nz)
+    k = 2 * math.pi / nz
+    tau_A, tau_B, delta = 1.4, 0.7, 0.1
+    rho = np.stack([np.full(N, 0.5 * (1 + phi)), np.full(N, 0.5 * (1 - phi))])
+    u = np.zeros((3, N))
+    u[0] = 1e-3 * np.sin(k * Z)
+    o = make(nx, ny, nz, 2, rho, u, tau_A=tau_A, tau_B=tau_B, G=0.0, delta=delta)
+    row = Y == ny // 2
+
+    def amp():
+        _, uu, _ = o.get_fields()
+        return 2.0 / nz * np.sum(uu[0][row] * np.sin(k * Z[row]))
+
+    assert o.step(100) == 0
+    a1 = amp()
+    assert o.step(200) == 0
+    a2 = amp()
+    nu = -math.log(a2 / a1) / (k * k * 200)
+    tau = tau_B + (tau_A - tau_B) * 0.5 * (1.0 + math.tanh(phi / delta))
+    assert abs(nu - (tau - 0.5) / 3.0) < 3e-3 * (tau - 0.5) / 3.0, (nu, (tau - 0.5) / 3.0)
+
+
+def _one_node_state(C6, nx=3, ny=3, nz=3, u=None):
+    """Unit-density one-component lattice at rest whose centre node holds C6 (all others
+    C = I)."""
+    N = nx * ny * nz
+    C = np.zeros((6, N))
+    C[:3] = 1.0
+    centre = ((nz // 2) * ny + ny // 2) * nx + nx // 2
+    C[:, centre] = C6
+    return np.ones((1, N)), (np.zeros((3, N)) if u is None else u), C
+
+
+@pytest.mark.parametrize("C6,flag", [
+    # leading minors 1, 1 and det = 0.19 - 0.81 < 0 (xz = yz = 0.9)
+    ([1.0, 1.0, 1.0, 0.0, 0.9, 0.9], oracle.FLAG_NOT_SPD),
+    # det < 0 with unequal couplings: 0.91 - 0.2 (0.2 + 0.285) + 0.95 (-0.06 - 0.95) = -0.147
+    ([1.0, 1.0, 1.0, 0.2, 0.95, -0.3], oracle.FLAG_NOT_SPD),
+    # second minor 1 - 1.44 < 0
+    ([1.0, 1.0, 1.0, 1.2, 0.0, 0.0], oracle.FLAG_NOT_SPD),
+    # second minor negative while the determinant (-0.44)(-1) is positive: only the second
+    # minor shows it
+    ([1.0, 1.0, -1.0, 1.2, 0.0, 0.0], oracle.FLAG_NOT_SPD),
+    # SPD close to the boundary (det = 0.8236 - 0.81 = 0.0136 > 0): no flag
+    ([1.0, 1.0, 1.0, 0.0, 0.9, 0.42], 0),
+    # first minor negative
+    ([-0.2, 1.0, 1.0, 0.0, 0.0, 0.0], oracle.FLAG_NOT_SPD),
+    # tr C above L^2 = 100
+    ([98.0, 1.5, 1.5, 0.0, 0.0, 0.0], oracle.FLAG_EXTENSIBILITY),
+])
+def test_fault_checks_raise_each_flag(C6, flag):
+    """S11: a state with one node outside the admissible set raises exactly the flag of
+    the violated condition after a step (the oracle never clips; flags: non-finite 1,
+    tr C >= L^2 2, a leading principal minor <= 0 4).  tau_P = 1e6 leaves C almost unchanged
+    over the step; the determinant of each SPD-violating case is checked against numpy's,
+    so the expected flag follows from linear algebra, not from the oracle's own formula."""
+    xx, yy, zz, xy, xz, yz = C6
+    M = np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]])
+    spd = M[0, 0] > 0 and np.linalg.det(M[:2, :2]) > 0 and np.linalg.det(M) > 0
+    assert spd == (flag != oracle.FLAG_NOT_SPD)
+    rho, u, C = _one_node_state(C6)
+    o = make(3, 3, 3, 1, rho, u, C, polymer_phase="none", tau_p=1e6, L2=100.0)
+    assert o.step(1) == flag
+    if flag:
+        assert o.steps == 1 and o.diagnostics()["flags"] == flag
+
+
+def test_fault_checks_non_finite_and_driven_extensibility():
+    """S11 raised by the dynamics: a NaN in C flags non-finite; one step of strong shear
+    takes tr C past L^2 = 10 (flag 2 alone: C stays finite and SPD); a
+    relaxation time tau_P = 0.3 below one step makes forward Euler overshoot C = diag(3,
+    0.3, 0.3) to a negative C_xx (flag 4 alone)."""
+    rho, u, C = _one_node_state([np.nan, 1.0, 1.0, 0.0, 0.0, 0.0])
+    o = make(3, 3, 3, 1, rho, u, C, polymer_phase="none", tau_p=100.0, L2=100.0)
+    assert o.step(1) & oracle.FLAG_NONFINITE
+    # FENE-P's f(r) diverges as tr C -> L^2, so a slow drive never crosses it; one step of
+    # shear gdot = 0.625 on C_xy = 2 adds 2 gdot C_xy = 2.5 to C_xx: tr C 8 -> 10.5 > L^2 = 10,
+    # while C stays SPD (second minor 8.5 - 2.625^2 = 1.61)
+    nx, ny, nz = 3, 4, 3
+    N = nx * ny * nz
+    _, Y, _ = coords(nx, ny, nz)
+    gdot = 0.625
+    U = gdot * ny / 2
+    u = np.zeros((3, N))
+    u[0] = gdot * (Y - (ny - 1) / 2)
+    C = np.zeros((6, N))
+    C[0], C[1], C[2], C[3] = 6.0, 1.0, 1.0, 2.0
+    o = oracle.Oracle(nx, ny, nz, 1)
+    o.set_params(polymer_phase="none", tau_p=1e4, L2=10.0)
+    o.set_walls([-U, 0, 0], [U, 0, 0])
+    o.set_fields(np.ones((1, N)), u, C)
+    assert o.step(5) == oracle.FLAG_EXTENSIBILITY and o.steps == 1
+    rho, u, C = _one_node_state([3.0, 0.3, 0.3, 0.0, 0.0, 0.0])
+    o = make(3, 3, 3, 1, rho, u, C, polymer_phase="none", tau_p=0.3, L2=100.0)
+    assert o.step(1) == oracle.FLAG_NOT_SPD
+
+
+def test_velocity_momentum_and_trace_diagnostics_on_known_fields():
+    """Diagnostics on fields whose values are known by construction (no force acts: G = 0
+    and no polymer feedback, so u is the u the populations were set from):
+    max |u| is the largest speed put in, 0.05 at one node; the momentum is sum (rho_A +
+    rho_B) u, here the total mass times a uniform drift plus that node's excess; the
+    polymer-phase mean of tr C - 3 is the mean over the nodes of the polymer's phase
+    (rho of the other species 1e-6, so f+-(phi) = 1 or 0 to 1e-8): 0.6 for phase A and 5.0
+    for phase B."""
+    nx, ny, nz = 8, 6, 4
+    N = nx * ny * nz
+    X, Y, Z = coords(nx, ny, nz)
+    a_rich = X < 4
+    rho = np.stack([np.where(a_rich, 1.0, 1e-6), np.where(a_rich, 1e-6, 0.8)])
+    u = np.zeros((3, N))
+    u[0] = 0.01
+    spot = 17
+    u[:, spot] = [0.03, -0.04, 0.0]
+    C = np.zeros((6, N))
+    C[:3] = 1.0
+    C[0] = np.where(a_rich, 1.6, 6.0)  # tr C - 3 = 0.6 on the A side, 5.0 on the B side
+    for phase, expect in (("A", 0.6), ("B", 5.0)):
+        o = make(nx, ny, nz, 2, rho, u, C, G=0.0, polymer_phase=phase, eta_p=0.0, tau_p=1e6)
+        d = o.diagnostics()
+        assert abs(d["max_u"] - 0.05) < 1e-15
+        mass = rho.sum()
+        rs = rho.sum(0)[spot]
+        assert abs(d["mom_x"] - (0.01 * mass + (0.03 - 0.01) * rs)) < 1e-12
+        assert abs(d["mom_y"] - (-0.04 * rs)) < 1e-15 and abs(d["mom_z"]) < 1e-15
+        assert abs(d["poly_trace_excess"] - expect) < 1e-6, (phase, d["poly_trace_excess"])
