@@ -30,6 +30,24 @@ __host__ __device__ constexpr float wgt(int a) {
     return a == 0 ? 1.0f / 3.0f : (a <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
 }
 
+// A weight as the FP32 pair w = hi + lo (hi the FP32 value nearest the weight, lo the rest),
+// and the same for 3w.  Products with the weights are formed as fma(lo, x, hi x), which puts
+// the weight itself into a single rounding.  hi x alone would scale every term of one
+// direction class by the same factor (1/3 rounds up by 3e-8 relative, 1/18 and 1/36 by
+// 7e-9), and a collision built on it would create mass in proportion to delta rho and
+// momentum in proportion to rho u at every step, coherently across the lattice.
+struct Wt {
+    float w, wl, w3, w3l;
+};
+__host__ __device__ constexpr double wexact(int a) {
+    return a == 0 ? 1.0 / 3.0 : (a <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+__host__ __device__ constexpr Wt wsplit(int a) {
+    return Wt{(float)wexact(a), (float)(wexact(a) - (double)(float)wexact(a)), (float)(3.0 * wexact(a)),
+              (float)(3.0 * wexact(a) - (double)(float)(3.0 * wexact(a)))};
+}
+__device__ __forceinline__ float wmul(float hi, float lo, float x) { return fmaf(lo, x, hi * x); }
+
 // symmetric 3x3 tensor component index in (xx, yy, zz, xy, xz, yz) order
 __host__ __device__ constexpr int sidx(int i, int j) {
     return i == j ? i : ((i + j) == 1 ? 3 : ((i + j) == 2 ? 4 : 5));

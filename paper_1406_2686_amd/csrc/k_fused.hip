@@ -391,9 +391,10 @@ __device__ __forceinline__ CollideIn collide_in(const DevParams& p, TL& L, int s
 // rest population: h - (h - h_eq)/tau + (1 - 1/(2 tau)) S
 __device__ __forceinline__ float collide_rest(const CollideIn& c, float ha) {
 #pragma clang fp contract(off)
-    const float w = wgt(0);
-    const float heq0 = w * fmaf(c.rs, c.b, c.drs) + (c.stress ? (4.5f * w) * c.trs3 : 0.0f);
-    return fmaf(c.cfac, w * (-3.0f * c.uF), fmaf(-c.om, ha - heq0, ha));
+    constexpr Wt w = wsplit(0);
+    const float heq0 = wmul(w.w, w.wl, fmaf(c.rs, c.b, c.drs)) + (c.stress ? 1.5f * c.trs3 : 0.0f);
+    // the rest source is w_0 (-3 u.F) = -u.F exactly
+    return fmaf(c.cfac, -c.uF, fmaf(-c.om, ha - heq0, ha));
 }
 
 // Opposite pair (a, a+1), c_{a+1} = -c_a, given c_a = (ex, ey, ez) and its weight w: the
@@ -402,26 +403,26 @@ __device__ __forceinline__ float collide_rest(const CollideIn& c, float ha) {
 // keeps the species mass drift smallest.  Fixed fma pattern, contraction off: the result
 // is the same whether c_a is a compile-time constant (own nodes) or a run-time value (the
 // tile-edge lanes that collide a halo node's inbound directions).
-__device__ __forceinline__ void collide_pair_c(const CollideIn& c, float ex, float ey, float ez, float w, float ha,
-                                               float hb, float& pa, float& pb) {
+__device__ __forceinline__ void collide_pair_c(const CollideIn& c, float ex, float ey, float ez, const Wt& w,
+                                               float ha, float hb, float& pa, float& pb) {
 #pragma clang fp contract(off)
     const float cu = fmaf(ez, c.u[2], fmaf(ey, c.u[1], ex * c.u[0]));
     const float cF = fmaf(ez, c.F[2], fmaf(ey, c.F[1], ex * c.F[0]));
-    float ee = w * fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs);  // equilibrium, even part
+    float ee = wmul(w.w, w.wl, fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs));  // equilibrium, even part
     if (c.stress) {
         const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
                           2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
-        ee = fmaf(-4.5f * w, cTc - c.trs3, ee);
+        ee = fmaf(-4.5f * w.w, cTc - c.trs3, ee);  // 4.5 w rounds to 1/4 or 1/8 exactly
     }
-    const float eo = ((3.0f * w) * c.rs) * cu;                 // equilibrium, odd part
-    const float se = w * fmaf(9.0f * cu, cF, -3.0f * c.uF);    // source, even part
-    const float so = (3.0f * w) * cF;                          // source, odd part
+    const float eo = wmul(w.w3, w.w3l, c.rs * cu);                      // equilibrium, odd part
+    const float se = wmul(w.w, w.wl, fmaf(9.0f * cu, cF, -3.0f * c.uF));  // source, even part
+    const float so = wmul(w.w3, w.w3l, cF);                             // source, odd part
     pa = fmaf(c.cfac, se + so, fmaf(-c.om, ha - (ee + eo), ha));
     pb = fmaf(c.cfac, se - so, fmaf(-c.om, hb - (ee - eo), hb));
 }
 
 __device__ __forceinline__ void collide_pair(const CollideIn& c, int a, float ha, float hb, float& pa, float& pb) {
-    collide_pair_c(c, float(cx(a)), float(cy(a)), float(cz(a)), wgt(a), ha, hb, pa, pb);
+    collide_pair_c(c, float(cx(a)), float(cy(a)), float(cz(a)), wsplit(a), ha, hb, pa, pb);
 }
 
 // MRT collision (Sec. 2) with every rate 1 except the bulk and shear modes (rate 1/tau):
@@ -458,7 +459,8 @@ __device__ __forceinline__ Mrt mrt_coef(const CollideIn& c, const float (&h)[kQ]
         if (cx(a) * cz(a) > 0) sxz += h[a];
         if (cx(a) * cz(a) < 0) sxz -= h[a];
     }
-    const float d3 = c.drs * (1.0f / 3.0f);
+    constexpr Wt third = wsplit(0);  // 1/3 as a split weight
+    const float d3 = wmul(third.w, third.wl, c.drs);
     const float* u = c.u;
     const float* F = c.F;
     const float gxx = (sxx - (fmaf(c.rs * u[0], u[0], d3) - c.Ts[0])) + u[0] * F[0];
@@ -478,20 +480,20 @@ __device__ __forceinline__ Mrt mrt_coef(const CollideIn& c, const float (&h)[kQ]
 // or compile-time direction: the rows are exact small integers either way).  The
 // equilibrium and the source split into parts even and odd in c, and the mode sum
 // (1 - 1/tau) P2 g is even in c, so the pair shares everything but the odd parts.
-__device__ __forceinline__ void mrt_pair_c(const CollideIn& c, const Mrt& m, float ex, float ey, float ez, float w,
-                                           float& pa, float& pb) {
+__device__ __forceinline__ void mrt_pair_c(const CollideIn& c, const Mrt& m, float ex, float ey, float ez,
+                                           const Wt& w, float& pa, float& pb) {
 #pragma clang fp contract(off)
     const float cu = fmaf(ez, c.u[2], fmaf(ey, c.u[1], ex * c.u[0]));
     const float cF = fmaf(ez, c.F[2], fmaf(ey, c.F[1], ex * c.F[0]));
-    float ee = w * fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs);  // equilibrium, even part
+    float ee = wmul(w.w, w.wl, fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs));  // equilibrium, even part
     if (c.stress) {
         const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
                           2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
-        ee = fmaf(-4.5f * w, cTc - c.trs3, ee);
+        ee = fmaf(-4.5f * w.w, cTc - c.trs3, ee);  // 4.5 w rounds to 1/4, 1/8 or 3/2 exactly
     }
-    const float eo = ((3.0f * w) * c.rs) * cu;                 // equilibrium, odd part
-    const float se = w * fmaf(9.0f * cu, cF, -3.0f * c.uF);    // source, even part
-    const float so = (3.0f * w) * cF;                          // source, odd part
+    const float eo = wmul(w.w3, w.w3l, c.rs * cu);                      // equilibrium, odd part
+    const float se = wmul(w.w, w.wl, fmaf(9.0f * cu, cF, -3.0f * c.uF));  // source, even part
+    const float so = wmul(w.w3, w.w3l, cF);                             // source, odd part
     const float c2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
     float r = fmaf(19.0f, c2, -30.0f) * m.e;
     r = fmaf(fmaf(3.0f * ex, ex, -c2), m.xx, r);
@@ -505,7 +507,7 @@ __device__ __forceinline__ void mrt_pair_c(const CollideIn& c, const Mrt& m, flo
     pb = ev - od;
 }
 __device__ __forceinline__ void mrt_pair(const CollideIn& c, const Mrt& m, int a, float& pa, float& pb) {
-    mrt_pair_c(c, m, float(cx(a)), float(cy(a)), float(cz(a)), wgt(a), pa, pb);
+    mrt_pair_c(c, m, float(cx(a)), float(cy(a)), float(cz(a)), wsplit(a), pa, pb);
 }
 
 // the pairs with c_x != 0 (their odd member has c_x = +1): 1, 7, 9, 11, 13
@@ -961,7 +963,7 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
                 const float ex = 1.0f;
                 const float ey = ap == 7 ? 1.0f : (ap == 9 ? -1.0f : 0.0f);
                 const float ez = ap == 11 ? 1.0f : (ap == 13 ? -1.0f : 0.0f);
-                const float w = ap == 1 ? wgt(1) : wgt(7);
+                const Wt w = ap == 1 ? wsplit(1) : wsplit(7);
                 const uint32_t hx = (uint32_t)wrapn(x0 + nlx, nx);  // halo column
                 const uint32_t bo = (zrow[1] + (uint32_t)(y0 + nly) * (uint32_t)nx + hx) * 4u;
                 const CollideIn in = collide_in<NC, TX, TY, TP>(p, L, sr, p2, comp, (nly + 1) * T::W1 + nlx + 1,

@@ -417,7 +417,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
         auto eq_src = [&](int a, float& heq, float& src) {
             const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
             const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
-            heq = wgt(a) * (drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+            const Wt w = wsplit(a);
+            heq = wmul(w.w, w.wl, drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
             if (stress_eq) {
                 const float cTc = float(cx(a) * cx(a)) * Ts[0] + float(cy(a) * cy(a)) * Ts[1] +
                                   float(cz(a) * cz(a)) * Ts[2] +
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
                                           float(cy(a) * cz(a)) * Ts[5]);
                 heq -= 4.5f * wgt(a) * (cTc - trs3);
             }
-            src = wgt(a) * (3.0f * (cF - uFd) + 9.0f * cu * cF);
+            src = wmul(w.w, w.wl, 3.0f * (cF - uFd) + 9.0f * cu * cF);
         };
         if constexpr (COLL == 1) {
             // MRT (Sec. 2): with every rate 1 except the bulk and shear modes (rate om), the
