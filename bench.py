@@ -120,10 +120,30 @@ def cpu_baseline(workloads, nx, ny, nz, budget_s=12.0, collision="bgk", fene="up
     if keep is not None:
         keep.update(wl=wl, steps=steps, fields=o.get_fields(), diag=o.diagnostics(),
                     desc=f"{bx}x{ny}x{bz} window at the centre of the {nx}x{ny}x{nz} droplet workload")
-    return {"value": nodes * steps / el / 1e6, "unit": "MLUPS", "cores": oracle.threads(),
+    cores = oracle.threads()
+    # the same window on one thread, two steps (the oracle's results do not depend on it)
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    o.step(2)
+    el1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    return {"value": nodes * steps / el / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} steps of a {bx}x{ny}x{bz} window of the same droplet workload "
-                      f"({nodes} nodes, FP64, {el:.1f} s)"}
+                      f"({nodes} nodes, FP64, {el:.1f} s)",
+            "cpu_model": cpu_model(),
+            "one_thread_MLUPS": round(nodes * 2 / el1 / 1e6, 3),
+            "one_thread_sample": f"2 further steps of the same window on 1 thread ({el1:.1f} s)"}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def sweep_judgement(plain, cold, paths, tol_d=0.01):
@@ -182,8 +202,20 @@ def fp32_vs_fp64(lb, ref, path_id):
 
 
 def copy_probe(torch, gib, reps=20):
-    """Plain device-to-device copy of `gib` GiB: bytes moved = 2 x size per copy.  Gives
-    the achievable HBM bandwidth and, under rocprofv3 --pmc, the byte-counter scale."""
+    """The library's streaming probe kernels (read, write, copy; plain and nontemporal
+    stores; 16-byte accesses) over `gib` GiB buffers: the HBM rates a plain streaming kernel
+    reaches on this part.  Then a plain device-to-device copy of `gib` GiB (bytes moved =
+    2 x size per copy), whose FETCH_SIZE / WRITE_SIZE counters under rocprofv3 --pmc give the
+    byte-counter scale."""
+    import paper_1406_2686_amd as lb
+
+    nbytes = int(gib * (1 << 30))
+    rates = {}
+    for kind in ("read", "write", "write_nt", "copy", "copy_nt"):
+        r = lb.stream_probe(kind, nbytes, reps=reps)
+        rates[kind] = {"ms": round(r["ms"], 4), "GB_per_s": round(r["GB_per_s"], 1),
+                       "frac_of_peak": round(r["GB_per_s"] / HBM_PEAK_GBS, 4)}
+    print(json.dumps({"stream_probe_GiB": gib, "kernels": rates}), flush=True)
     n = int(gib * (1 << 30)) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)

@@ -194,7 +194,9 @@ lbfd_status lbfd_get_fields(lbfd_ctx* ctx, double* rho, double* u, double* C);
 lbfd_status lbfd_get_fields_box(lbfd_ctx* ctx, int32_t x0, int32_t y0, int32_t z0, int32_t bx,
                                 int32_t by, int32_t bz, double* rho, double* u, double* C);
 
-/* FP64 diagnostics record of the current state.  Synchronises the stream. */
+/* FP64 diagnostics record of the current state, on demand (there is no diagnostics cadence
+ * in lbfd_params: a caller steps in chunks and calls this between them; the batch's steady
+ * test carries its own cadence in lbfd_steady_crit).  Synchronises the stream. */
 lbfd_status lbfd_diagnostics(lbfd_ctx* ctx, lbfd_diag* out);
 
 /* For callers that cannot allocate device memory (code under stream capture, tight
@@ -279,9 +281,15 @@ typedef struct {
     int32_t reserved;   /* 0 */
 } lbfd_steady_crit;
 
+/* Wall velocities of one batch instance (as lbfd_set_walls). */
+typedef struct {
+    double u_bottom[3];
+    double u_top[3];
+} lbfd_walls;
+
 lbfd_status lbfd_batch_state_bytes(int32_t n, const lbfd_grid* grids, uint64_t* bytes);
-/* params: n entries; walls: n x 6 doubles (u_bottom[3], u_top[3]) per instance. */
-lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_params* params, const double* walls,
+/* params, walls: n entries each. */
+lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_params* params, const lbfd_walls* walls,
                               void* dev_state, uint64_t bytes, void* hip_stream, lbfd_batch** out);
 /* Fields of instance i, as lbfd_set_fields. */
 lbfd_status lbfd_batch_set_fields(lbfd_batch* b, int32_t i, const double* rho, const double* u, const double* C);
@@ -359,10 +367,30 @@ lbfd_status lbfd_mlp_adam_step(lbfd_mlp* m, const lbfd_train_opts* opts);
  * of the last minibatch. */
 lbfd_status lbfd_mlp_train(lbfd_mlp* m, const float* X, const float* T, int32_t n, const lbfd_train_opts* opts,
                            float* final_loss);
-/* BF16 inference (weights rounded to BF16 once after each update). */
+/* BF16 inference (weights rounded to BF16 once after each update); the inference call of
+ * the surrogate (named for its arithmetic, since lbfd_mlp_forward is the FP32 forward pass). */
 lbfd_status lbfd_mlp_infer_bf16(lbfd_mlp* m, const float* X, int32_t n, float* Y);
 void lbfd_mlp_destroy(lbfd_mlp* m);
 const char* lbfd_mlp_last_error(const lbfd_mlp* m);
+
+/* ---------------------------------------------------------------------------------
+ * Streaming-bandwidth probe: the read, write and copy rates a plain streaming kernel reaches
+ * on the current device, the ceiling against which the step's traffic is judged (every
+ * lane moves 16-byte vectors; grid-stride loops at 8 waves per SIMD).  kind: one of the
+ * LBFD_PROBE_*; src and dst are caller-owned device buffers of `bytes` bytes (a multiple
+ * of 16, 16-byte aligned; src unused by the write kinds, dst by the read kind).  Runs one
+ * warm-up launch, then times `reps` launches with HIP events on `hip_stream` and returns
+ * the mean milliseconds per launch (bytes moved per launch: `bytes` for read and write,
+ * 2 x `bytes` for copy).  EINVAL for a bad argument, EDEVICE on a HIP error.
+ * Synchronises the stream.
+ * --------------------------------------------------------------------------------- */
+#define LBFD_PROBE_READ 0
+#define LBFD_PROBE_WRITE 1     /* plain stores */
+#define LBFD_PROBE_WRITE_NT 2  /* nontemporal (streaming) stores */
+#define LBFD_PROBE_COPY 3
+#define LBFD_PROBE_COPY_NT 4
+lbfd_status lbfd_stream_probe(int32_t kind, void* dev_src, void* dev_dst, uint64_t bytes, int32_t reps,
+                              void* hip_stream, double* ms_per_launch);
 
 /* Library build/version string (static). */
 const char* lbfd_version(void);

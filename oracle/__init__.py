@@ -88,6 +88,7 @@ def lib():
         L.orc_get_C.argtypes = [P, D]
         L.orc_set_C.argtypes = [P, D]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -95,6 +96,11 @@ def lib():
 def threads() -> int:
     """OpenMP threads the oracle uses (OMP_NUM_THREADS or all cores)."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (its results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 def _dp(a: np.ndarray):

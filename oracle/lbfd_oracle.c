@@ -939,6 +939,9 @@ void orc_set_C(orc_t *o, const double *C) { memcpy(o->C, C, sizeof(double) * 6 *
 #ifdef _OPENMP
 #include <omp.h>
 int orc_threads(void) { return omp_get_max_threads(); }
+/* threads of the following parallel regions (results do not depend on it) */
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 #else
 int orc_threads(void) { return 1; }
+void orc_set_threads(int n) { (void)n; }
 #endif

@@ -72,6 +72,10 @@ class Diag(ctypes.Structure):
                 "poly_trace_excess": self.poly_trace_excess}
 
 
+class Walls(ctypes.Structure):
+    _fields_ = [("u_bottom", ctypes.c_double * 3), ("u_top", ctypes.c_double * 3)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("zchunk", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -121,7 +125,7 @@ class SteadyCrit(ctypes.Structure):
 
 _sig("lbfd_autotune", [_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)])
 _sig("lbfd_batch_state_bytes", [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_uint64)])
-_sig("lbfd_batch_create", [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params), _D, _P,
+_sig("lbfd_batch_create", [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.POINTER(Walls), _P,
                            ctypes.c_uint64, _P, ctypes.POINTER(_P)])
 _sig("lbfd_batch_set_fields", [_P, ctypes.c_int32, _D, _D, _D])
 _sig("lbfd_batch_set_tuning", [_P, ctypes.POINTER(Tuning)])
@@ -156,6 +160,27 @@ _sig("lbfd_mlp_infer_bf16", [_P, _F, ctypes.c_int32, _F])
 _sig("lbfd_mlp_destroy", [_P], None)
 _sig("lbfd_mlp_last_error", [_P], ctypes.c_char_p)
 _sig("lbfd_version", [], ctypes.c_char_p)
+_sig("lbfd_stream_probe", [ctypes.c_int32, _P, _P, ctypes.c_uint64, ctypes.c_int32, _P,
+                           ctypes.POINTER(ctypes.c_double)])
+PROBES = {"read": 0, "write": 1, "write_nt": 2, "copy": 3, "copy_nt": 4}
+
+
+def stream_probe(kind: str, nbytes: int, reps: int = 20, device="cuda") -> dict:
+    """HBM streaming rate of the library's probe kernel `kind` (read, write, write_nt, copy,
+    copy_nt) over buffers of nbytes each: ms per launch and GB/s of bytes moved."""
+    import torch
+
+    nbytes = nbytes // 16 * 16
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    ms = ctypes.c_double(0)
+    stream = torch.cuda.current_stream(src.device)
+    st = _lib.lbfd_stream_probe(PROBES[kind], _P(src.data_ptr()), _P(dst.data_ptr()), ctypes.c_uint64(nbytes),
+                                int(reps), _P(stream.cuda_stream), ctypes.byref(ms))
+    if st != OK:
+        raise LbfdError(st, "lbfd_stream_probe")
+    moved = nbytes * (2 if kind.startswith("copy") else 1)
+    return {"kind": kind, "bytes": moved, "ms": ms.value, "GB_per_s": moved / (ms.value * 1e-3) / 1e9}
 _sig("lbfd_destroy", [_P], None)
 _sig("lbfd_last_error", [_P], ctypes.c_char_p)
 
@@ -372,9 +397,8 @@ class Batch:
         grids = (Grid * self.n)(*[Grid(w["grid"]["nx"], w["grid"]["ny"], w["grid"]["nz"],
                                        w["grid"]["ncomp"]) for w in workloads_list])
         params = (Params * self.n)(*[make_params(**w["params"]) for w in workloads_list])
-        walls = np.ascontiguousarray(
-            [list(w["walls"]["u_bottom"]) + list(w["walls"]["u_top"]) for w in workloads_list],
-            dtype=np.float64)
+        walls = (Walls * self.n)(*[Walls((ctypes.c_double * 3)(*w["walls"]["u_bottom"]),
+                                         (ctypes.c_double * 3)(*w["walls"]["u_top"])) for w in workloads_list])
         nb = ctypes.c_uint64(0)
         st = _lib.lbfd_batch_state_bytes(self.n, grids, ctypes.byref(nb))
         if st != OK:
@@ -384,7 +408,7 @@ class Batch:
         self._stream = torch.cuda.Stream(device=self.device)
         h = _P()
         with torch.cuda.device(self.device):
-            st = _lib.lbfd_batch_create(self.n, grids, params, _dp(walls), _P(aligned), nb,
+            st = _lib.lbfd_batch_create(self.n, grids, params, walls, _P(aligned), nb,
                                         _P(self._stream.cuda_stream), ctypes.byref(h))
         if st != OK:
             raise LbfdError(st, "lbfd_batch_create failed")

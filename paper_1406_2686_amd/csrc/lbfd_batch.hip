@@ -239,7 +239,7 @@ lbfd_status lbfd_batch_state_bytes(int32_t n, const lbfd_grid* grids, uint64_t* 
     return LBFD_OK;
 }
 
-lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_params* params, const double* walls,
+lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_params* params, const lbfd_walls* walls,
                               void* dev_state, uint64_t bytes, void* hip_stream, lbfd_batch** out) {
     if (!out) return LBFD_EINVAL;
     *out = nullptr;
@@ -266,7 +266,7 @@ lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_para
         lbfd_state_bytes(&grids[i], &sb);
         lbfd_ctx* c = nullptr;
         st = lbfd_create(&grids[i], &params[i], p, sb, hip_stream, &c);
-        if (st == LBFD_OK) st = lbfd_set_walls(c, walls + 6 * i, walls + 6 * i + 3);
+        if (st == LBFD_OK) st = lbfd_set_walls(c, walls[i].u_bottom, walls[i].u_top);
         if (st != LBFD_OK) {
             if (c) lbfd_destroy(c);
             for (lbfd_ctx* q : b->inst) lbfd_destroy(q);

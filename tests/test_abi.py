@@ -67,7 +67,8 @@ def test_struct_offsets_match_the_compiled_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
     pairs = [("lbfd_grid", lb.Grid), ("lbfd_params", lb.Params), ("lbfd_diag", lb.Diag),
-             ("lbfd_tuning", lb.Tuning), ("lbfd_steady_crit", lb.SteadyCrit), ("lbfd_train_opts", lb.TrainOpts)]
+             ("lbfd_tuning", lb.Tuning), ("lbfd_steady_crit", lb.SteadyCrit), ("lbfd_train_opts", lb.TrainOpts),
+             ("lbfd_walls", lb.Walls)]
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lbfd.h"', "int main(void) {"]
     for cname, py in pairs:
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
