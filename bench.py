@@ -146,33 +146,38 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def sweep_judgement(plain, cold, paths, tol_d=0.01):
-    """Which held-out answers count, and the fastest sweep path whose answers are all within
-    tol_d of the plain per-case solves.  plain, cold: solver results (D, steady_step,
-    wall_s) of the per-case sweep and of the batched cold solve; paths: name -> (seconds, D
+def sweep_judgement(plain, alt, paths, tol_d=0.01):
+    """The answers of every sweep path against the plain per-case solves, and the fastest
+    path whose answers are all within tol_d.
+
+    plain: the per-case sweep on the library's default launch path, the chained step (the
+    batched solve runs the same tile body, instance by instance bit for bit); alt: the
+    per-case sweep on launch shapes autotuned per grid shape, a different rounding of the
+    same steps.  Both are dicts with D, steady_step and wall_s.  paths: name -> (seconds, D
     per case) of the candidate paths.
 
-    Judged cases are those the plain sweep brought to steady D, except those whose answer
-    depends on the launch shape.  The batched solve runs the chained body, and each of its
-    instances equals a single chained lattice bit for bit; where its answer and the plain
-    solve's (the autotuned shape) differ by more than tol_d, rounding has decided the branch
-    (a marginally stable droplet that stays or breaks up), and no shape reproduces another's."""
+    Every path is judged on every case the plain sweep brought to steady D, and only a path
+    within tol_d on all of them qualifies.  Cases whose two plain answers differ by more
+    than tol_d are reported as shape-sensitive (rounding decides their branch: a marginally
+    stable droplet that stays or breaks up); that split is made from the two plain sweeps
+    alone, and the scores over the remaining cases are reported beside the gating ones."""
     import numpy as np
 
     steady = np.asarray(plain["steady_step"]) > 0
     ref = np.asarray(plain["D"], dtype=np.float64)
-    shape_sensitive = steady & (np.abs(np.asarray(cold["D"]) - ref) > tol_d)
-    valid = steady & ~shape_sensitive
+    shape_sensitive = steady & (np.abs(np.asarray(alt["D"], dtype=np.float64) - ref) > tol_d)
+    rest = steady & ~shape_sensitive
 
     def within(d, mask):
-        return float(np.mean(np.abs(np.asarray(d) - ref)[mask] <= tol_d)) if mask.any() else 1.0
+        return float(np.mean(np.abs(np.asarray(d, dtype=np.float64) - ref)[mask] <= tol_d)) if mask.any() else 1.0
 
-    scores = {k: (t, within(d, valid)) for k, (t, d) in paths.items()}
-    scores["plain"] = (plain["wall_s"], 1.0)
-    best = min((t, k) for k, (t, w) in scores.items() if w >= 1.0)
-    return {"valid": valid, "shape_sensitive": shape_sensitive, "best": best,
-            "within": {k: w for k, (t, w) in scores.items() if k != "plain"},
-            "within_all_steady": {k: within(d, steady) for k, (t, d) in paths.items()}}
+    allp = dict(paths)
+    allp["plain_tuned"] = (alt["wall_s"], alt["D"])
+    gate = {k: within(d, steady) for k, (t, d) in allp.items()}
+    cands = [(t, k) for k, (t, d) in allp.items() if gate[k] >= 1.0] + [(plain["wall_s"], "plain")]
+    return {"steady": steady, "shape_sensitive": shape_sensitive, "best": min(cands),
+            "within_all_steady": gate,
+            "within_shape_insensitive": {k: within(d, rest) for k, (t, d) in allp.items()}}
 
 
 def fp32_vs_fp64(lb, ref, path_id):
@@ -267,8 +272,10 @@ def sweep(lb, workloads, args):
     t0 = time.perf_counter()
     losses = [m.fit(X, Y, epochs=400, batch=128, lr=2e-3, seed=s + 10) for s, m in enumerate(models)]
     t_train = time.perf_counter() - t0
-    plain = sg.solve_plain(lb, wtest, progress=log, **crit)
-    log(f"plain sweep: {plain['wall_s']:.1f} s")
+    plain = sg.solve_plain(lb, wtest, progress=log, tune="chained", **crit)
+    log(f"plain sweep (chained path): {plain['wall_s']:.1f} s")
+    alt = sg.solve_plain(lb, wtest, progress=log, tune="cached", **crit)
+    log(f"plain sweep (shapes tuned per grid): {alt['wall_s']:.1f} s + tuning {alt['tuning_s']:.1f} s")
     cold = sg.solve(lb, wtest, progress=log, **crit)
     log(f"batched cold sweep: {cold['wall_s']:.1f} s")
     t0 = time.perf_counter()
@@ -285,32 +292,34 @@ def sweep(lb, workloads, args):
         answer[idx] = fb["D"]
         t_fb = fb["wall_s"]
     log(f"surrogate + fallback: {flag.sum()} of {len(test)} solved, {t_pred + t_fb:.2f} s")
-    J = sweep_judgement(plain, cold, {"surrogate_with_fallback": (t_pred + t_fb, answer),
-                                      "batched_cold": (cold["wall_s"], cold["D"])})
-    valid, shape_sensitive, judge = J["valid"], J["shape_sensitive"], plain["D"]
+    # the surrogate's time counts its training data and training; the time without them
+    # (both amortised over later sweeps) is printed beside it
+    t_sur = gen["wall_s"] + t_train + t_pred + t_fb
+    J = sweep_judgement(plain, alt, {"surrogate_with_fallback": (t_sur, answer),
+                                     "surrogate_alone": (gen["wall_s"] + t_train + t_pred, pred[:, 0]),
+                                     "batched_cold": (cold["wall_s"], cold["D"])})
     if args.save_data:
         np.savez(args.save_data, X_train=sg.features(train), Y_train=np.stack([gen["D"], gen["theta"], gen["amp"]], 1),
-                 steady_train=gen["steady_step"], X_test=sg.features(test), D_plain=plain["D"],
+                 steady_train=gen["steady_step"], X_test=sg.features(test), D_plain=plain["D"], D_tuned=alt["D"],
                  steady_plain=plain["steady_step"], D_cold=cold["D"], pred1=p1, pred2=p2)
-    within = lambda d: float(np.mean(np.abs(d - judge)[valid] <= 0.01))
+    steady = J["steady"]
     best = J["best"]
     out = {"metric": "sweep time-to-steady-D (|dD| <= 0.01 against plain solves)", "unit": "s",
            "value": round(best[0], 3), "path": best[1], "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic", "dtype": "f32 solver, bf16 surrogate inference",
            "config": {"workload": f"droplet sweep, grids x{args.scale} of 64-192 x 32-64",
                       "n_train": len(train), "n_test": len(test), **crit},
-           "plain_per_case_s": round(plain["wall_s"], 2), "batched_cold_s": round(cold["wall_s"], 2),
+           "plain_per_case_s": round(plain["wall_s"], 2), "plain_tuned_s": round(alt["wall_s"], 2),
+           "plain_tuning_s": round(alt["tuning_s"], 2), "batched_cold_s": round(cold["wall_s"], 2),
+           "batched_equals_plain": bool(np.array_equal(cold["D"], plain["D"])),
+           "surrogate_end_to_end_s": round(t_sur, 2), "surrogate_amortised_s": round(t_pred + t_fb, 2),
            "surrogate_infer_s": round(t_pred, 4), "fallback_solve_s": round(t_fb, 2),
            "fallback_cases": int(flag.sum()), "training_data_s": round(gen["wall_s"], 2),
            "train_s": round(t_train, 2), "final_loss": losses,
-           "judged_cases": int(valid.sum()), "shape_sensitive_cases": int(shape_sensitive.sum()),
-           "within_0.01": {"surrogate_with_fallback": within(answer), "surrogate_alone": within(pred[:, 0]),
-                           "batched_cold": within(cold["D"])},
-           # the same over every case the plain sweep brought to steady D, shape-sensitive ones
-           # included (the batched solve's own check is its bitwise equality with single
-           # chained lattices, which the tests verify)
+           "steady_cases": int(steady.sum()), "shape_sensitive_cases": int(J["shape_sensitive"].sum()),
            "within_0.01_all_steady": J["within_all_steady"],
-           "surrogate_mean_abs_dD": float(np.abs(pred[:, 0] - judge)[valid].mean()),
+           "within_0.01_shape_insensitive": J["within_shape_insensitive"],
+           "surrogate_mean_abs_dD": float(np.abs(pred[:, 0] - plain["D"])[steady].mean()),
            "unsteady_or_fault": {"plain": int((plain["steady_step"] <= 0).sum()),
                                  "cold": int((cold["steady_step"] <= 0).sum()),
                                  "training": int((~ok).sum())}}
@@ -331,23 +340,29 @@ def sweep_solver_only(lb, workloads, args, crit):
         w["params"].update(collision=args.collision, fene=args.fene, coupling=args.coupling, kappa=args.kappa)
     nodes = [c["nx"] * c["ny"] * c["nz"] for c in cases]
     log(f"solver-only sweep: {len(cases)} cases, scale {args.scale}, {sum(nodes) / 1e6:.1f} M nodes")
-    plain = sg.solve_plain(lb, wls, progress=log, **crit)
-    log(f"plain sweep: {plain['wall_s']:.1f} s")
+    plain = sg.solve_plain(lb, wls, progress=log, tune="chained", **crit)
+    log(f"plain sweep (chained path): {plain['wall_s']:.1f} s")
+    alt = sg.solve_plain(lb, wls, progress=log, tune="cached", **crit)
+    log(f"plain sweep (shapes tuned per grid): {alt['wall_s']:.1f} s + tuning {alt['tuning_s']:.1f} s")
     cold = sg.solve(lb, wls, progress=log, **crit)
     log(f"batched cold sweep: {cold['wall_s']:.1f} s")
-    J = sweep_judgement(plain, cold, {"batched_cold": (cold["wall_s"], cold["D"])})
+    J = sweep_judgement(plain, alt, {"batched_cold": (cold["wall_s"], cold["D"])})
     steps_p = np.where(plain["steady_step"] > 0, plain["steady_step"], args.max_steps)
+    fastest_plain = min(plain["wall_s"], alt["wall_s"])
     out = {"metric": "sweep time-to-steady-D (|dD| <= 0.01 against plain solves)", "unit": "s",
            "value": round(J["best"][0], 3), "path": J["best"][1], "higher_is_better": False, "n_gpus": 1,
            "data": "synthetic", "dtype": "f32",
            "config": {"workload": f"{len(cases)} droplet-in-shear instances (seed 3), grids x{args.scale} of "
                                   f"64-192 x 32-64", "nodes_total": int(sum(nodes)), "collision": args.collision,
                       "fene": args.fene, "coupling": args.coupling, "kappa": args.kappa, **crit},
-           "plain_per_case_s": round(plain["wall_s"], 2), "batched_cold_s": round(cold["wall_s"], 2),
-           "speedup": round(plain["wall_s"] / cold["wall_s"], 2),
+           "plain_per_case_s": round(plain["wall_s"], 2), "plain_tuned_s": round(alt["wall_s"], 2),
+           "plain_tuning_s": round(alt["tuning_s"], 2), "batched_cold_s": round(cold["wall_s"], 2),
+           "batched_equals_plain": bool(np.array_equal(cold["D"], plain["D"])),
+           "speedup_vs_fastest_plain": round(fastest_plain / cold["wall_s"], 2),
            "plain_MLUPS": round(float(np.dot(nodes, steps_p)) / plain["wall_s"] / 1e6, 1),
-           "judged_cases": int(J["valid"].sum()), "shape_sensitive_cases": int(J["shape_sensitive"].sum()),
-           "within_0.01": J["within"], "within_0.01_all_steady": J["within_all_steady"],
+           "steady_cases": int(J["steady"].sum()), "shape_sensitive_cases": int(J["shape_sensitive"].sum()),
+           "within_0.01_all_steady": J["within_all_steady"],
+           "within_0.01_shape_insensitive": J["within_shape_insensitive"],
            "unsteady": {"plain": int((plain["steady_step"] == -1).sum()), "cold": int((cold["steady_step"] == -1).sum())},
            "fault": {"plain": int((plain["steady_step"] == -2).sum()), "cold": int((cold["steady_step"] == -2).sum())}}
     print(json.dumps(out), flush=True)

@@ -39,23 +39,31 @@ def test_recorded_traffic_follows_the_source_hash(tmp_path, monkeypatch):
 
 
 def test_sweep_judgement():
+    """Every path is judged on every case the plain sweep brought to steady D, and gated on
+    that; shape sensitivity comes from the two plain sweeps alone and is only reported."""
     plain = {"D": np.array([0.10, 0.20, 0.30, 0.40, 0.05]), "steady_step": np.array([900, 800, -1, 700, 600]),
              "wall_s": 70.0}
-    # case 3 is shape-sensitive (the chained body takes the other branch); case 2 never
-    # became steady in the plain sweep
-    cold = {"D": np.array([0.10, 0.2005, 0.9, 0.47, 0.05]), "wall_s": 27.0}
+    # the autotuned plain sweep takes the other branch on case 3; case 2 never became steady
+    alt = {"D": np.array([0.10, 0.2001, 0.31, 0.47, 0.05]), "wall_s": 60.0}
+    cold = {"D": plain["D"].copy(), "wall_s": 27.0}          # the batch equals the chained plain sweep
     surrogate = np.array([0.105, 0.23, 0.3, 0.4, 0.05])
-    J = bench.sweep_judgement(plain, cold, {"surrogate_with_fallback": (20.0, surrogate),
-                                            "batched_cold": (cold["wall_s"], cold["D"])})
+    J = bench.sweep_judgement(plain, alt, {"surrogate_with_fallback": (20.0, surrogate),
+                                           "batched_cold": (cold["wall_s"], cold["D"])})
     assert J["shape_sensitive"].tolist() == [False, False, False, True, False]
-    assert J["valid"].tolist() == [True, True, False, False, True]
-    assert J["within"]["batched_cold"] == 1.0
-    assert abs(J["within"]["surrogate_with_fallback"] - 2 / 3) < 1e-12   # case 1 is off by 0.03
-    assert J["best"] == (27.0, "batched_cold")                           # fastest path within 0.01
-    assert abs(J["within_all_steady"]["batched_cold"] - 0.75) < 1e-12
-    # nothing faster qualifies: the plain sweep answers itself
-    J2 = bench.sweep_judgement(plain, cold, {"batched_cold": (27.0, cold["D"] + 0.02)})
-    assert J2["best"] == (70.0, "plain")
+    assert J["steady"].tolist() == [True, True, False, True, True]
+    assert J["within_all_steady"]["batched_cold"] == 1.0
+    assert J["within_all_steady"]["plain_tuned"] == 0.75           # off by 0.07 on case 3: counted
+    assert J["within_all_steady"]["surrogate_with_fallback"] == 0.75  # off by 0.03 on case 1
+    assert J["within_shape_insensitive"]["plain_tuned"] == 1.0
+    assert J["best"] == (27.0, "batched_cold")
+    # a batched answer off on the shape-sensitive case does not qualify
+    off = cold["D"].copy()
+    off[3] = 0.47
+    J2 = bench.sweep_judgement(plain, alt, {"batched_cold": (27.0, off)})
+    assert J2["within_all_steady"]["batched_cold"] == 0.75 and J2["best"] == (70.0, "plain")
+    # with agreeing plain sweeps, the tuned one is the faster qualifying path
+    J3 = bench.sweep_judgement(plain, dict(alt, D=plain["D"] + 0.001), {"batched_cold": (80.0, cold["D"])})
+    assert J3["best"] == (60.0, "plain_tuned")
 
 
 class _StubLattice:
@@ -99,9 +107,9 @@ def test_per_case_steady_test_over_consecutive_windows(monkeypatch):
     monkeypatch.setitem(sys.modules, "torch", torch_stub)
     plateau = [0.10, 0.12, 0.13, 0.13, 0.13, 0.15, 0.18, 0.20, 0.20, 0.20, 0.20, 0.20, 0.20]
     one = sg.solve_plain(_StubLb([plateau]), [None], every=100, window=200, tol=1e-3, max_steps=5000,
-                         autotune=False, windows=1)
+                         tune="chained", windows=1)
     two = sg.solve_plain(_StubLb([plateau]), [None], every=100, window=200, tol=1e-3, max_steps=5000,
-                         autotune=False, windows=2)
+                         tune="chained", windows=2)
     # one window: samples 3 and 5 (t = 300, 500) agree -> steady at t = 500, D = 0.13
     assert one["steady_step"][0] == 500 and one["D"][0] == 0.13
     # two windows: samples t - 400, t - 200, t all agree only from t = 1200 on
@@ -109,5 +117,5 @@ def test_per_case_steady_test_over_consecutive_windows(monkeypatch):
     # never settling: not steady (-1) after max_steps
     ramp = [0.01 * k for k in range(1, 80)]
     r = sg.solve_plain(_StubLb([ramp]), [None], every=100, window=200, tol=1e-3, max_steps=3000,
-                       autotune=False, windows=2)
+                       tune="chained", windows=2)
     assert r["steady_step"][0] == -1
