@@ -21,6 +21,10 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
         "or `python paper_1406_2686_amd/build.py` (hipcc, gfx950)")
 
+# torch carries its own HIP runtime library; it is loaded first so that the library binds to
+# that one (a second runtime loaded for the library would not see torch's device memory)
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EEXTENSIBILITY, ENOTSPD, ESTATE = range(8)
