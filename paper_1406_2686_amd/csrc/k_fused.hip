@@ -397,6 +397,19 @@ __device__ __forceinline__ float collide_rest(const CollideIn& c, float ha) {
     return fmaf(c.cfac, -c.uF, fmaf(-c.om, ha - heq0, ha));
 }
 
+// The odd part of the equilibrium of one direction, 3 w rho (c.u), rounded once: rho (c.u) is
+// carried as the exact pair rc + rce (the product's rounding error recovered with an fma).  A
+// steady node rounds this product the same way at every step, and the rounding of rho (c.u)
+// alone acted as a fixed, node-by-node momentum source; the channel's slowest flow mode
+// integrated it into a relative velocity error that grew to 1e-5 within a thousand steps of the
+// 128 x 64 x 128 droplet.
+__device__ __forceinline__ float odd_equilibrium(const Wt& w, float rs, float cu) {
+#pragma clang fp contract(off)
+    const float rc = rs * cu;
+    const float rce = fmaf(rs, cu, -rc);
+    return fmaf(w.w3, rc, fmaf(w.w3, rce, w.w3l * rc));
+}
+
 // Opposite pair (a, a+1), c_{a+1} = -c_a, given c_a = (ex, ey, ez) and its weight w: the
 // equilibrium and the source split into parts even and odd in c, formed once; each
 // population is relaxed as h - (h - h_eq)/tau + (1 - 1/(2 tau)) S, the form whose rounding
@@ -414,7 +427,7 @@ __device__ __forceinline__ void collide_pair_c(const CollideIn& c, float ex, flo
                           2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
         ee = fmaf(-4.5f * w.w, cTc - c.trs3, ee);  // 4.5 w rounds to 1/4 or 1/8 exactly
     }
-    const float eo = wmul(w.w3, w.w3l, c.rs * cu);                      // equilibrium, odd part
+    const float eo = odd_equilibrium(w, c.rs, cu);  // equilibrium, odd part
     const float se = wmul(w.w, w.wl, fmaf(9.0f * cu, cF, -3.0f * c.uF));  // source, even part
     const float so = wmul(w.w3, w.w3l, cF);                             // source, odd part
     pa = fmaf(c.cfac, se + so, fmaf(-c.om, ha - (ee + eo), ha));
@@ -491,7 +504,7 @@ __device__ __forceinline__ void mrt_pair_c(const CollideIn& c, const Mrt& m, flo
                           2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
         ee = fmaf(-4.5f * w.w, cTc - c.trs3, ee);  // 4.5 w rounds to 1/4, 1/8 or 3/2 exactly
     }
-    const float eo = wmul(w.w3, w.w3l, c.rs * cu);                      // equilibrium, odd part
+    const float eo = odd_equilibrium(w, c.rs, cu);  // equilibrium, odd part
     const float se = wmul(w.w, w.wl, fmaf(9.0f * cu, cF, -3.0f * c.uF));  // source, even part
     const float so = wmul(w.w3, w.w3l, cF);                             // source, odd part
     const float c2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));

@@ -418,7 +418,12 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
             const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
             const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
             const Wt w = wsplit(a);
-            heq = wmul(w.w, w.wl, drs + rs * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+            // even part, then the odd part 3 w rho (c.u) with rho (c.u) carried exactly
+            // (rc + rce) and rounded once, as in the tile body
+            const float rc = rs * cu;
+            const float rce = fmaf(rs, cu, -rc);
+            heq = wmul(w.w, w.wl, drs + rs * (4.5f * cu * cu - 1.5f * uu)) +
+                  fmaf(w.w3, rc, fmaf(w.w3, rce, w.w3l * rc));
             if (stress_eq) {
                 const float cTc = float(cx(a) * cx(a)) * Ts[0] + float(cy(a) * cy(a)) * Ts[1] +
                                   float(cz(a) * cz(a)) * Ts[2] +

@@ -81,6 +81,19 @@ def test_droplet_128x64x128_full_grid(lb, variant):
     assert abs(dg["poly_trace_excess"] - do["poly_trace_excess"]) < 1e-4 * max(1e-3, abs(do["poly_trace_excess"]))
 
 
+@pytest.mark.parametrize("De", [0.1, 0.5, 1.0])
+def test_droplet_128x64x128_1000_steps_each_De(lb, De):
+    """The viscoelastic droplet of 2R/H = 0.5 on the full 128x64x128 grid (G at the binodal,
+    polymer in the droplet, Ca = 0.2), 1000 steps at each Deborah number of the sweep: u, C,
+    C - I and the densities within 1e-5 relative L2 of the FP64 oracle, and every diagnostics
+    field within the bounds its field differences allow."""
+    wl = workloads.droplet_cfg1(De=De, variant="physics")
+    g, r, dg, do = run_both(lb, wl, 1000)
+    e = report(f"cfg1-1000-De{De:g}", g, r)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["C-I"] < 1e-5 and e["rho"] < 1e-5, e
+    check_diag(dg, do, f"cfg1-1000-De{De:g}", g, r, grid_shape(wl), wl["params"])
+
+
 @pytest.mark.parametrize("case", ["polyA", "polyB", "visc_ratio", "ragged"])
 def test_droplet_long_runs(lb, case):
     """Smaller droplets over 1500 steps: polymer in droplet / matrix, viscosity ratio
