@@ -31,11 +31,13 @@ __host__ __device__ constexpr float wgt(int a) {
 }
 
 // A weight as the FP32 pair w = hi + lo (hi the FP32 value nearest the weight, lo the rest),
-// and the same for 3w.  Products with the weights are formed as fma(lo, x, hi x), which puts
-// the weight itself into a single rounding.  hi x alone would scale every term of one
-// direction class by the same factor (1/3 rounds up by 3e-8 relative, 1/18 and 1/36 by
-// 7e-9), and a collision built on it would create mass in proportion to delta rho and
-// momentum in proportion to rho u at every step, coherently across the lattice.
+// and the same for 3w.  Products with the weights are formed as fma(hi, x, lo x): the exact
+// product hi x plus the small lo x, rounded once, so the weight itself enters the result.
+// hi x alone would scale every term of one direction class by the same factor (1/3 rounds
+// up by 3e-8 relative, 1/18 and 1/36 by 7e-9), and a collision built on it would create
+// mass in proportion to delta rho and momentum in proportion to rho u at every step,
+// coherently across the lattice.  (The other order, fma(lo, x, hi x), rounds hi x first and
+// then adds lo x to a value already rounded: a term below half an ulp of it is lost.)
 struct Wt {
     float w, wl, w3, w3l;
 };
@@ -46,7 +48,7 @@ __host__ __device__ constexpr Wt wsplit(int a) {
     return Wt{(float)wexact(a), (float)(wexact(a) - (double)(float)wexact(a)), (float)(3.0 * wexact(a)),
               (float)(3.0 * wexact(a) - (double)(float)(3.0 * wexact(a)))};
 }
-__device__ __forceinline__ float wmul(float hi, float lo, float x) { return fmaf(lo, x, hi * x); }
+__device__ __forceinline__ float wmul(float hi, float lo, float x) { return fmaf(hi, x, lo * x); }
 
 // symmetric 3x3 tensor component index in (xx, yy, zz, xy, xz, yz) order
 __host__ __device__ constexpr int sidx(int i, int j) {

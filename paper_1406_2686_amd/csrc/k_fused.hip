@@ -388,13 +388,14 @@ __device__ __forceinline__ CollideIn collide_in(const DevParams& p, TL& L, int s
     return c;
 }
 
-// rest population: h - (h - h_eq)/tau + (1 - 1/(2 tau)) S
+// rest population: h + [(1 - 1/(2 tau)) S - (h - h_eq)/tau]
 __device__ __forceinline__ float collide_rest(const CollideIn& c, float ha) {
 #pragma clang fp contract(off)
     constexpr Wt w = wsplit(0);
-    const float heq0 = wmul(w.w, w.wl, fmaf(c.rs, c.b, c.drs)) + (c.stress ? 1.5f * c.trs3 : 0.0f);
+    const float x0 = fmaf(c.rs, c.b, c.drs);
+    const float heq0 = fmaf(w.w, x0, fmaf(w.wl, x0, c.stress ? 1.5f * c.trs3 : 0.0f));
     // the rest source is w_0 (-3 u.F) = -u.F exactly
-    return fmaf(c.cfac, -c.uF, fmaf(-c.om, ha - heq0, ha));
+    return ha + fmaf(c.cfac, -c.uF, -c.om * (ha - heq0));
 }
 
 // The odd part of the equilibrium of one direction, 3 w rho (c.u), rounded once: rho (c.u) is
@@ -403,35 +404,51 @@ __device__ __forceinline__ float collide_rest(const CollideIn& c, float ha) {
 // alone acted as a fixed, node-by-node momentum source; the channel's slowest flow mode
 // integrated it into a relative velocity error that grew to 1e-5 within a thousand steps of the
 // 128 x 64 x 128 droplet.
-__device__ __forceinline__ float odd_equilibrium(const Wt& w, float rs, float cu) {
+// `extra` is a small term of the same parity that joins it before that rounding.
+__device__ __forceinline__ float odd_equilibrium(const Wt& w, float rs, float cu, float extra = 0.0f) {
 #pragma clang fp contract(off)
     const float rc = rs * cu;
     const float rce = fmaf(rs, cu, -rc);
-    return fmaf(w.w3, rc, fmaf(w.w3, rce, w.w3l * rc));
+    return fmaf(w.w3, rc, fmaf(w.w3, rce, fmaf(w.w3l, rc, extra)));
+}
+
+// The even part of the equilibrium of one direction, w (delta rho + rho (4.5 (c.u)^2 - 1.5
+// u^2)), with the stress term of eq. MODEtransformation when that coupling is on, and a small
+// even term `extra`, rounded once.
+__device__ __forceinline__ float even_equilibrium(const CollideIn& c, float ex, float ey, float ez, const Wt& w,
+                                                  float cu, float extra = 0.0f) {
+#pragma clang fp contract(off)
+    const float xe = fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs);
+    float lo = fmaf(w.wl, xe, extra);
+    if (c.stress) {
+        const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
+                          2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
+        lo = fmaf(-4.5f * w.w, cTc - c.trs3, lo);  // 4.5 w rounds to 1/4, 1/8 or 3/2 exactly
+    }
+    return fmaf(w.w, xe, lo);
 }
 
 // Opposite pair (a, a+1), c_{a+1} = -c_a, given c_a = (ex, ey, ez) and its weight w: the
-// equilibrium and the source split into parts even and odd in c, formed once; each
-// population is relaxed as h - (h - h_eq)/tau + (1 - 1/(2 tau)) S, the form whose rounding
-// keeps the species mass drift smallest.  Fixed fma pattern, contraction off: the result
-// is the same whether c_a is a compile-time constant (own nodes) or a run-time value (the
-// tile-edge lanes that collide a halo node's inbound directions).
+// equilibrium and the source split into parts even and odd in c, formed once.  Each
+// population is relaxed as h + [(1 - 1/(2 tau)) S - (h - h_eq)/tau]: the increment is formed
+// first and added to h once.  In the form fma(1 - 1/(2 tau), S, h - (h - h_eq)/tau) the
+// source was added to a value already rounded at the scale of h, and a source below half an
+// ulp of h was dropped; it was dropped the same way at every step and in every plane of a
+// sheared flow, so the lost force acted coherently and the channel's slowest mode integrated
+// it.  Fixed fma pattern, contraction off: the result is the same whether c_a is a
+// compile-time constant (own nodes) or a run-time value (the tile-edge lanes that collide a
+// halo node's inbound directions).
 __device__ __forceinline__ void collide_pair_c(const CollideIn& c, float ex, float ey, float ez, const Wt& w,
                                                float ha, float hb, float& pa, float& pb) {
 #pragma clang fp contract(off)
     const float cu = fmaf(ez, c.u[2], fmaf(ey, c.u[1], ex * c.u[0]));
     const float cF = fmaf(ez, c.F[2], fmaf(ey, c.F[1], ex * c.F[0]));
-    float ee = wmul(w.w, w.wl, fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs));  // equilibrium, even part
-    if (c.stress) {
-        const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
-                          2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
-        ee = fmaf(-4.5f * w.w, cTc - c.trs3, ee);  // 4.5 w rounds to 1/4 or 1/8 exactly
-    }
-    const float eo = odd_equilibrium(w, c.rs, cu);  // equilibrium, odd part
+    const float ee = even_equilibrium(c, ex, ey, ez, w, cu);             // equilibrium, even part
+    const float eo = odd_equilibrium(w, c.rs, cu);                       // equilibrium, odd part
     const float se = wmul(w.w, w.wl, fmaf(9.0f * cu, cF, -3.0f * c.uF));  // source, even part
     const float so = wmul(w.w3, w.w3l, cF);                             // source, odd part
-    pa = fmaf(c.cfac, se + so, fmaf(-c.om, ha - (ee + eo), ha));
-    pb = fmaf(c.cfac, se - so, fmaf(-c.om, hb - (ee - eo), hb));
+    pa = ha + fmaf(c.cfac, se + so, -c.om * (ha - (ee + eo)));
+    pb = hb + fmaf(c.cfac, se - so, -c.om * (hb - (ee - eo)));
 }
 
 __device__ __forceinline__ void collide_pair(const CollideIn& c, int a, float ha, float hb, float& pa, float& pb) {
@@ -492,19 +509,15 @@ __device__ __forceinline__ Mrt mrt_coef(const CollideIn& c, const float (&h)[kQ]
 // Post-collision populations of the opposite pair c_a = (ex, ey, ez), c_b = -c_a (a run-time
 // or compile-time direction: the rows are exact small integers either way).  The
 // equilibrium and the source split into parts even and odd in c, and the mode sum
-// (1 - 1/tau) P2 g is even in c, so the pair shares everything but the odd parts.
+// (1 - 1/tau) P2 g is even in c, so the pair shares everything but the odd parts.  The small
+// terms (the source and the mode sum) join each part before its one rounding: added to a
+// part already rounded, a term below half an ulp of it would be dropped, the same way at
+// every step.
 __device__ __forceinline__ void mrt_pair_c(const CollideIn& c, const Mrt& m, float ex, float ey, float ez,
                                            const Wt& w, float& pa, float& pb) {
 #pragma clang fp contract(off)
     const float cu = fmaf(ez, c.u[2], fmaf(ey, c.u[1], ex * c.u[0]));
     const float cF = fmaf(ez, c.F[2], fmaf(ey, c.F[1], ex * c.F[0]));
-    float ee = wmul(w.w, w.wl, fmaf(c.rs, fmaf(4.5f * cu, cu, c.b), c.drs));  // equilibrium, even part
-    if (c.stress) {
-        const float cTc = fmaf(ex * ex, c.Ts[0], fmaf(ey * ey, c.Ts[1], ez * ez * c.Ts[2])) +
-                          2.0f * fmaf(ex * ey, c.Ts[3], fmaf(ex * ez, c.Ts[4], ey * ez * c.Ts[5]));
-        ee = fmaf(-4.5f * w.w, cTc - c.trs3, ee);  // 4.5 w rounds to 1/4, 1/8 or 3/2 exactly
-    }
-    const float eo = odd_equilibrium(w, c.rs, cu);  // equilibrium, odd part
     const float se = wmul(w.w, w.wl, fmaf(9.0f * cu, cF, -3.0f * c.uF));  // source, even part
     const float so = wmul(w.w3, w.w3l, cF);                             // source, odd part
     const float c2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
@@ -514,8 +527,8 @@ __device__ __forceinline__ void mrt_pair_c(const CollideIn& c, const Mrt& m, flo
     r = fmaf(ex * ey, m.xy, r);
     r = fmaf(ey * ez, m.yz, r);
     r = fmaf(ex * ez, m.xz, r);
-    const float ev = fmaf(0.5f, se, ee) + r;
-    const float od = fmaf(0.5f, so, eo);
+    const float ev = even_equilibrium(c, ex, ey, ez, w, cu, fmaf(0.5f, se, r));  // E + S/2 + r, even part
+    const float od = odd_equilibrium(w, c.rs, cu, 0.5f * so);                  // E + S/2, odd part
     pa = ev + od;
     pb = ev - od;
 }

@@ -422,15 +422,17 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
             // (rc + rce) and rounded once, as in the tile body
             const float rc = rs * cu;
             const float rce = fmaf(rs, cu, -rc);
-            heq = wmul(w.w, w.wl, drs + rs * (4.5f * cu * cu - 1.5f * uu)) +
-                  fmaf(w.w3, rc, fmaf(w.w3, rce, w.w3l * rc));
+            // the even part with the stress term of eq. MODEtransformation, rounded once
+            float st = 0.0f;
             if (stress_eq) {
                 const float cTc = float(cx(a) * cx(a)) * Ts[0] + float(cy(a) * cy(a)) * Ts[1] +
                                   float(cz(a) * cz(a)) * Ts[2] +
                                   2.0f * (float(cx(a) * cy(a)) * Ts[3] + float(cx(a) * cz(a)) * Ts[4] +
                                           float(cy(a) * cz(a)) * Ts[5]);
-                heq -= 4.5f * wgt(a) * (cTc - trs3);
+                st = -4.5f * wgt(a) * (cTc - trs3);
             }
+            const float xe = drs + rs * (4.5f * cu * cu - 1.5f * uu);
+            heq = fmaf(w.w, xe, fmaf(w.wl, xe, st)) + fmaf(w.w3, rc, fmaf(w.w3, rce, w.w3l * rc));
             src = wmul(w.w, w.wl, 3.0f * (cF - uFd) + 9.0f * cu * cF);
         };
         if constexpr (COLL == 1) {
@@ -440,15 +442,18 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
             // P2 the orthogonal projection on the modes e, 3p_xx, p_ww, p_xy, p_yz, p_xz of
             // the D3Q19 basis (rows 19c^2 - 30, 3c_x^2 - c^2, c_y^2 - c_z^2, c_x c_y, c_y c_z,
             // c_x c_z; squared norms 2394, 36, 12, 4, 4, 4)
-            float base[kQ];
+            // f* = h + [S/2 + (1 - om) P2 g - (h - E)]: the increment is formed first and added
+            // to h once (a small term added to a value already rounded at the scale of h is
+            // dropped when below half an ulp of it)
+            float hv[kQ];
             float pe = 0.f, pxx = 0.f, pww = 0.f, pxy = 0.f, pyz = 0.f, pxz = 0.f;
 #pragma unroll
             for (int a = 0; a < kQ; ++a) {
                 float heq, src;
                 eq_src(a, heq, src);
                 const float ha = hs[a * N + n];
+                hv[a] = ha;
                 const float g = ha - heq + 0.5f * src;
-                base[a] = heq + 0.5f * src;
                 const int c2 = cx(a) * cx(a) + cy(a) * cy(a) + cz(a) * cz(a);
                 pe += float(19 * c2 - 30) * g;
                 if (3 * cx(a) * cx(a) - c2 != 0) pxx += float(3 * cx(a) * cx(a) - c2) * g;
@@ -467,12 +472,15 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
 #pragma unroll
             for (int a = 0; a < kQ; ++a) {
                 const int c2 = cx(a) * cx(a) + cy(a) * cy(a) + cz(a) * cz(a);
-                float post = base[a] + float(19 * c2 - 30) * pe;
-                if (3 * cx(a) * cx(a) - c2 != 0) post += float(3 * cx(a) * cx(a) - c2) * pxx;
-                if (cy(a) * cy(a) - cz(a) * cz(a) != 0) post += float(cy(a) * cy(a) - cz(a) * cz(a)) * pww;
-                if (cx(a) * cy(a) != 0) post += float(cx(a) * cy(a)) * pxy;
-                if (cy(a) * cz(a) != 0) post += float(cy(a) * cz(a)) * pyz;
-                if (cx(a) * cz(a) != 0) post += float(cx(a) * cz(a)) * pxz;
+                float r = float(19 * c2 - 30) * pe;
+                if (3 * cx(a) * cx(a) - c2 != 0) r += float(3 * cx(a) * cx(a) - c2) * pxx;
+                if (cy(a) * cy(a) - cz(a) * cz(a) != 0) r += float(cy(a) * cy(a) - cz(a) * cz(a)) * pww;
+                if (cx(a) * cy(a) != 0) r += float(cx(a) * cy(a)) * pxy;
+                if (cy(a) * cz(a) != 0) r += float(cy(a) * cz(a)) * pyz;
+                if (cx(a) * cz(a) != 0) r += float(cx(a) * cz(a)) * pxz;
+                float heq, src;
+                eq_src(a, heq, src);
+                const float post = hv[a] + (fmaf(0.5f, src, r) - (hv[a] - heq));
                 check += post;
                 emit(a, post);
             }
@@ -487,7 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
                 const float ha = hv[a];
                 float heq, src;
                 eq_src(a, heq, src);
-                const float post = ha - om * (ha - heq) + cf * src;
+                // the increment first, added to h once (see the MRT branch)
+                const float post = ha + fmaf(cf, src, -om * (ha - heq));
                 check += post;
                 emit(a, post);
             }
