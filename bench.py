@@ -386,11 +386,13 @@ def batch_bench(lb, workloads, args):
     nodes = sum(w["grid"]["nx"] * w["grid"]["ny"] * w["grid"]["nz"] for w in wls)
     b = lb.Batch(wls)
     if args.path == "chained":
-        b.set_tuning("64x8", 0, path=lb.PATH_CHAINED)
+        b.set_tuning(args.tile or "64x8", 0, path=lb.PATH_CHAINED)
     elif args.path == "fused":
         b.set_tuning("32x8", 0, path=lb.PATH_FUSED)
     elif args.path != "default":
         raise SystemExit("--batch runs the fused or the chained path")
+    if args.path == "default" and args.tile:
+        b.set_tuning(args.tile, 0, path=lb.PATH_CHAINED)
     tune = b.get_tuning()
     b.step(args.warmup + args.warmup % 2)
     torch.cuda.synchronize()
@@ -486,6 +488,8 @@ def main():
                     help="sweep: write the training and held-out cases' features and solver answers (.npz)")
     ap.add_argument("--batch", type=int, default=0,
                     help="time the batched step over this many sweep lattices instead")
+    ap.add_argument("--tile", choices=["64x8", "32x16"], default=None,
+                    help="tile of the chained batch body (with --batch; default 64x8)")
     ap.add_argument("--mlp", action="store_true", help="time the surrogate network's kernels instead")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM calibration)")

@@ -241,7 +241,7 @@ lbfd_status lbfd_set_state(lbfd_ctx* ctx, const void* host, uint64_t bytes);
 #define LBFD_TILE_32x16 1
 #define LBFD_TILE_16x16 2
 #define LBFD_TILE_64x8 3   /* two-pass and chained steps only (one 64-lane row per wavefront);
-                              the fused and split steps and batches run it as 32x8 */
+                              the fused and split steps and fused batches run it as 32x8 */
 typedef struct {
     int32_t path;
     int32_t tile;
@@ -294,10 +294,12 @@ lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_para
 /* Fields of instance i, as lbfd_set_fields. */
 lbfd_status lbfd_batch_set_fields(lbfd_batch* b, int32_t i, const double* rho, const double* u, const double* C);
 /* path LBFD_PATH_FUSED (the single-pass body; tile and zchunk as for a single lattice,
- * zchunk >= 4 in a batch) or LBFD_PATH_CHAINED (the chained body on 64x8 tiles: each
- * instance's moments are carried from step to step; they are formed by the moments pass,
- * or copied between its two moments buffers, when an instance has none at its current
- * level).  Results of the two paths agree to FP32 rounding; within a path they do not
+ * zchunk >= 4 in a batch) or LBFD_PATH_CHAINED (the chained body: each instance's moments
+ * are carried from step to step; they are formed by the moments pass, or copied between
+ * its two moments buffers, when an instance has none at its current level; tile
+ * LBFD_TILE_32x16 runs 32x16 tiles, for lattices 32 or 96 nodes wide, every other tile
+ * value 64x8).  A new batch runs the chained body, on 32x16 tiles when its instances would
+ * leave 64x8 tiles emptier by a tenth of the lanes or more, else on 64x8.  Results of the two paths agree to FP32 rounding; within a path they do not
  * depend on the other instances or on tile and zchunk. */
 lbfd_status lbfd_batch_set_tuning(lbfd_batch* b, const lbfd_tuning* t);
 lbfd_status lbfd_batch_get_tuning(lbfd_batch* b, lbfd_tuning* t);

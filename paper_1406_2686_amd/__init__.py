@@ -450,7 +450,7 @@ class Batch:
 
     def set_tuning(self, tile="32x8", zchunk=0, path=PATH_FUSED):
         """Launch shape of the batched step: the fused body (tiles 32x8, 16x16) or the
-        chained body (path=PATH_CHAINED, 64x8 tiles)."""
+        chained body (path=PATH_CHAINED, tiles 64x8 or 32x16)."""
         t = Tuning(int(path), TILES[tile] if isinstance(tile, str) else int(tile), int(zchunk), 0)
         self._check(_lib.lbfd_batch_set_tuning(self._h, ctypes.byref(t)))
 

@@ -600,7 +600,8 @@ __device__ __forceinline__ void fused_tile(const DevParams& p, const float* __re
     using T = FusedTile<NC, TX, TY, TP, MO>;
     static_assert(FE == 0 || MO, "the Cholesky integrator runs in the chained body only");
     static_assert(CO == 0 || MO, "the MRT collision runs in the chained body only");
-    static_assert(!MO || (TP && TX == 64), "next-level moments: two-pass body, one tile row per wavefront");
+    static_assert(!MO || (TP && (TX == 64 || TX == 32)),
+                  "next-level moments: two-pass body, one or two tile rows per wavefront");
     static_assert(T::NH2 <= T::NT, "one R2 halo node per thread at most");
     static_assert(T::A1 <= 2 * T::NTH, "phase B covers the R1 region in two passes at most");
     static_assert(T::NT % 64 == 0, "a wavefront never straddles two components");
@@ -1344,21 +1345,27 @@ __global__ __launch_bounds__(NC* TX* TY, 1) void k_fused_batch(
                                          w.z0, w.z1, nullptr, nullptr);
 }
 
-// Chained step for many lattices: the k_fused_batch work table, 64x8 tiles, and each
-// instance's moments carried in mom[cur ^ parity] -> mom[cur ^ parity ^ 1] (and, with the
-// Cholesky integrator, its rate history in ab the same way).  FE and CO as for k_fused3,
-// shared by every instance of the batch.
-template <int NC, int FE, int CO>
+// Chained step for many lattices: the k_fused_batch work table, and each instance's moments
+// carried in mom[cur ^ parity] -> mom[cur ^ parity ^ 1] (and, with the Cholesky integrator,
+// its rate history in ab the same way).  FE and CO as for k_fused3, shared by every instance
+// of the batch.  TX = 64: 64x8 tiles, one tile row per wavefront; TX = 32: 32x16 tiles for
+// lattices 32 or 96 nodes wide, where a 64-wide tile would run half or a quarter empty (two
+// tile rows per wavefront, the shuffles 32 lanes wide; the wavefronts that collide a
+// neighbouring row run it in both halves, which form the same values).  The collisions and
+// the order in which each node's moments are summed do not depend on the tile, so both
+// shapes give the same results bit for bit.
+template <int NC, int FE, int CO, int TX>
 __global__ __launch_bounds__(NC * 64 * 8, NC == 2 ? 4 : 2) void k_fused3_batch(
     const BatchInstance* __restrict__ inst, const WorkItem* __restrict__ work, int parity) {
-    __shared__ FusedTile<NC, 64, 8, true, true> L;
+    constexpr int TY = 512 / TX;
+    __shared__ FusedTile<NC, TX, TY, true, true> L;
     const int64_t bid = xcd_remap_f(blockIdx.x, gridDim.x);
     const WorkItem w = work[bid];
     const BatchInstance& bi = inst[w.inst];
     const DevParams p = bi.p;
     const int c = bi.cur ^ parity;
-    fused_tile<NC, 64, 8, true, true, FE, CO>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0,
-                                              w.z0, w.z1, bi.mom[c], bi.mom[c ^ 1], bi.ab[c], bi.ab[c ^ 1]);
+    fused_tile<NC, TX, TY, true, true, FE, CO>(p, bi.h[c], bi.h[c ^ 1], bi.D[c], bi.D[c ^ 1], bi.flags, L, w.x0, w.y0,
+                                               w.z0, w.z1, bi.mom[c], bi.mom[c ^ 1], bi.ab[c], bi.ab[c ^ 1]);
 }
 
 template <int NC, int TX, int TY>
@@ -1432,26 +1439,38 @@ hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, i
 }
 
 template <int NC, int FE, int CO>
-static void launch_fused3_batch_t(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int parity,
+static void launch_fused3_batch_t(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int tx, int parity,
                                   hipStream_t s) {
-    hipLaunchKernelGGL((k_fused3_batch<NC, FE, CO>), dim3((unsigned)nwork), dim3(NC * 512), 0, s, inst, work, parity);
+    if (tx == 32)
+        hipLaunchKernelGGL((k_fused3_batch<NC, FE, CO, 32>), dim3((unsigned)nwork), dim3(NC * 512), 0, s, inst, work,
+                           parity);
+    else
+        hipLaunchKernelGGL((k_fused3_batch<NC, FE, CO, 64>), dim3((unsigned)nwork), dim3(NC * 512), 0, s, inst, work,
+                           parity);
 }
 
 hipError_t launch_fused3_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int fene,
-                               int collision, int parity, hipStream_t s) {
+                               int collision, int tx, int parity, hipStream_t s) {
     if (nwork <= 0) return hipSuccess;
+    if (tx != 32 && tx != 64) return hipErrorInvalidValue;
     const int sel = (ncomp == 2 ? 4 : 0) + (fene == 1 ? 2 : 0) + (collision == 1 ? 1 : 0);
     switch (sel) {
-        case 0: launch_fused3_batch_t<1, 0, 0>(inst, work, nwork, parity, s); break;
-        case 1: launch_fused3_batch_t<1, 0, 1>(inst, work, nwork, parity, s); break;
-        case 2: launch_fused3_batch_t<1, 1, 0>(inst, work, nwork, parity, s); break;
-        case 3: launch_fused3_batch_t<1, 1, 1>(inst, work, nwork, parity, s); break;
-        case 4: launch_fused3_batch_t<2, 0, 0>(inst, work, nwork, parity, s); break;
-        case 5: launch_fused3_batch_t<2, 0, 1>(inst, work, nwork, parity, s); break;
-        case 6: launch_fused3_batch_t<2, 1, 0>(inst, work, nwork, parity, s); break;
-        default: launch_fused3_batch_t<2, 1, 1>(inst, work, nwork, parity, s); break;
+        case 0: launch_fused3_batch_t<1, 0, 0>(inst, work, nwork, tx, parity, s); break;
+        case 1: launch_fused3_batch_t<1, 0, 1>(inst, work, nwork, tx, parity, s); break;
+        case 2: launch_fused3_batch_t<1, 1, 0>(inst, work, nwork, tx, parity, s); break;
+        case 3: launch_fused3_batch_t<1, 1, 1>(inst, work, nwork, tx, parity, s); break;
+        case 4: launch_fused3_batch_t<2, 0, 0>(inst, work, nwork, tx, parity, s); break;
+        case 5: launch_fused3_batch_t<2, 0, 1>(inst, work, nwork, tx, parity, s); break;
+        case 6: launch_fused3_batch_t<2, 1, 0>(inst, work, nwork, tx, parity, s); break;
+        default: launch_fused3_batch_t<2, 1, 1>(inst, work, nwork, tx, parity, s); break;
     }
     return hipGetLastError();
+}
+
+// tile extent of the chained batch body for a tuning choice: 32x16 when asked for, else 64x8
+void chained_batch_tile_shape(int tile, int* tx, int* ty) {
+    *tx = tile == 1 ? 32 : 64;
+    *ty = tile == 1 ? 16 : 8;
 }
 
 // tile extent of a tuning choice (the 32x16 choice runs as 32x8: a 32x16 tile with its

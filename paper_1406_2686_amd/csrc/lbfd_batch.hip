@@ -96,8 +96,11 @@ hipError_t upload_tables(lbfd_batch* b) {
     for (int i = 0; i < b->n; ++i) {
         if (!b->active[i]) continue;
         const lbfd_grid& g = b->inst[i]->grid;
-        int tx = 64, ty = 8;  // the chained batch step runs 64x8 tiles
-        if (b->tune.path != LBFD_PATH_CHAINED) fused_tile_shape(g.ncomp, b->tune.tile, &tx, &ty);
+        int tx = 64, ty = 8;
+        if (b->tune.path == LBFD_PATH_CHAINED)
+            chained_batch_tile_shape(b->tune.tile, &tx, &ty);
+        else
+            fused_tile_shape(g.ncomp, b->tune.tile, &tx, &ty);
         const int zc = batch_zchunk(b, g);
         for (int z0 = 0; z0 < g.nz; z0 += zc)
             for (int y0 = 0; y0 < g.ny; y0 += ty)
@@ -126,8 +129,11 @@ bool batch_options(const lbfd_batch* b, int* fene, int* collision) {
 hipError_t launch_batch(lbfd_batch* b, int parity) {
     int fene = 0, coll = 0;
     (void)batch_options(b, &fene, &coll);
-    if (b->tune.path == LBFD_PATH_CHAINED)
-        return launch_fused3_batch(b->d_inst, b->d_work, b->nwork, b->ncomp, fene, coll, parity, b->stream);
+    if (b->tune.path == LBFD_PATH_CHAINED) {
+        int tx = 64, ty = 8;
+        chained_batch_tile_shape(b->tune.tile, &tx, &ty);
+        return launch_fused3_batch(b->d_inst, b->d_work, b->nwork, b->ncomp, fene, coll, tx, parity, b->stream);
+    }
     return launch_fused_batch(b->d_inst, b->d_work, b->nwork, b->ncomp, b->tune.tile, parity, b->stream);
 }
 
@@ -254,9 +260,17 @@ lbfd_status lbfd_batch_create(int32_t n, const lbfd_grid* grids, const lbfd_para
     b->ncomp = grids[0].ncomp;
     b->stream = (hipStream_t)hip_stream;
     (void)hipGetDevice(&b->device);
-    // the chained body: 4.88 ms per step on the 255-lattice droplet sweep against 5.50 for
-    // the fused single-pass body on 32x8 tiles
-    b->tune = Tuning{LBFD_PATH_CHAINED, LBFD_TILE_64x8, 0};
+    // the chained body (4.88 ms per step on the 255-lattice droplet sweep against 5.50 for
+    // the fused single-pass body on 32x8 tiles), on 32x16 tiles when the instances leave
+    // 64x8 tiles emptier by a tenth of the lanes or more (4.70 against 5.13 ms per step on
+    // the same sweep, whose lattices are 32, 64 or 96 nodes wide)
+    int64_t lanes64 = 0, lanes32 = 0;
+    for (int i = 0; i < n; ++i) {
+        const lbfd_grid& g = grids[i];
+        lanes64 += (int64_t)((g.nx + 63) / 64 * 64) * ((g.ny + 7) / 8 * 8) * g.nz;
+        lanes32 += (int64_t)((g.nx + 31) / 32 * 32) * ((g.ny + 15) / 16 * 16) * g.nz;
+    }
+    b->tune = Tuning{LBFD_PATH_CHAINED, lanes32 * 11 <= lanes64 * 10 ? LBFD_TILE_32x16 : LBFD_TILE_64x8, 0};
     b->graph_ok = false;
     b->tables_dirty = true;
     char* p = (char*)dev_state;
@@ -443,8 +457,9 @@ lbfd_status lbfd_batch_autotune(lbfd_batch* b, int32_t reps, lbfd_tuning* best, 
     BCHK(b, hipEventCreate(&e0), "event");
     BCHK(b, hipEventCreate(&e1), "event");
     // (path, tile) choices: the fused body on 32x8 and 16x16 tiles, the chained body on 64x8
-    const int shapes[3][2] = {{LBFD_PATH_FUSED, LBFD_TILE_32x8}, {LBFD_PATH_FUSED, LBFD_TILE_16x16},
-                              {LBFD_PATH_CHAINED, LBFD_TILE_64x8}};
+    // and 32x16
+    const int shapes[4][2] = {{LBFD_PATH_FUSED, LBFD_TILE_32x8}, {LBFD_PATH_FUSED, LBFD_TILE_16x16},
+                              {LBFD_PATH_CHAINED, LBFD_TILE_64x8}, {LBFD_PATH_CHAINED, LBFD_TILE_32x16}};
     const int zcs[5] = {16, 32, 64, 128, 256};
     Tuning keep = b->tune, win = b->tune;
     float best_ms = 1e30f;

@@ -99,10 +99,12 @@ hipError_t launch_fused2(const DevParams& p, const Buffers& b, const Tuning& t, 
 hipError_t launch_fused3(const DevParams& p, const Buffers& b, const Tuning& t, hipStream_t s);
 hipError_t launch_fused_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int tile,
                               int parity, hipStream_t s);
-// chained step over a work table of 64x8 tiles (moments of level n in mom[cur ^ parity])
-// fene, collision: the options every instance of the batch shares (DevParams::fene, ::collision)
+// chained step over a work table of tx-wide tiles, tx 64 (64x8) or 32 (32x16) (moments of
+// level n in mom[cur ^ parity]); fene, collision: the options every instance of the batch
+// shares (DevParams::fene, ::collision)
 hipError_t launch_fused3_batch(const BatchInstance* inst, const WorkItem* work, int64_t nwork, int ncomp, int fene,
-                               int collision, int parity, hipStream_t s);
+                               int collision, int tx, int parity, hipStream_t s);
+void chained_batch_tile_shape(int tile, int* tx, int* ty);
 void fused_tile_shape(int ncomp, int tile, int* tx, int* ty);
 
 // field transfer kernels (k_fields.hip)

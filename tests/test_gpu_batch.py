@@ -70,14 +70,17 @@ def test_batch_matches_single_lattices_bitwise_over_graph_replays(lb):
     b.close()
 
 
-def test_chained_batch_matches_chained_single_lattices_bitwise(lb):
-    """The chained body over the batch work table (64x8 tiles, each instance's moments
-    carried from step to step in its own buffers) against single lattices on the chained
-    step: bitwise over graph replays, odd step counts, diagnostics in between, a retired
-    instance (its moments wait with it) and its return."""
+@pytest.mark.parametrize("tile", ["64x8", "32x16"])
+def test_chained_batch_matches_chained_single_lattices_bitwise(lb, tile):
+    """The chained body over the batch work table (64x8 or 32x16 tiles, each instance's
+    moments carried from step to step in its own buffers) against single lattices on the
+    chained step (64x8 tiles): bitwise over graph replays, odd step counts, diagnostics in
+    between, a retired instance (its moments wait with it) and its return.  The cases
+    include lattices narrower than a tile in x (16) and in y (8), and ragged ones."""
     cases = small_cases()
     b = lb.Batch(cases)
     assert b.get_tuning()["path"] == lb.PATH_CHAINED  # the default
+    b.set_tuning(tile, 0, path=lb.PATH_CHAINED)
     total = 0
     for n in (10, 7, 1):
         b.step(n)
@@ -99,9 +102,24 @@ def test_chained_batch_matches_chained_single_lattices_bitwise(lb):
     b.close()
 
 
-@pytest.mark.parametrize("collision,fene", [("mrt", "upwind_euler"), ("bgk", "cholesky_ab2"),
-                                           ("mrt", "cholesky_ab2")])
-def test_batches_with_the_papers_schemes_match_single_lattices_bitwise(lb, collision, fene):
+def test_default_chained_tile_follows_the_instance_widths(lb):
+    """A new batch runs the chained body on 32x16 tiles when its lattices would leave 64x8
+    tiles emptier by a tenth of the lanes or more (32 and 96 nodes wide), else on 64x8."""
+    G = workloads.G_PHYSICS_1_004
+    narrow = [workloads.droplet_shear(nx=32, ny=16, nz=16, R=4.0, G=G, U=0.01),
+              workloads.droplet_shear(nx=96, ny=16, nz=16, R=4.0, G=G, U=0.01)]
+    wide = [workloads.droplet_shear(nx=64, ny=16, nz=16, R=4.0, G=G, U=0.01),
+            workloads.droplet_shear(nx=128, ny=8, nz=16, R=3.0, G=G, U=0.01)]
+    for cases, tile in ((narrow, "32x16"), (wide, "64x8")):
+        b = lb.Batch(cases)
+        t = b.get_tuning()
+        assert t["path"] == lb.PATH_CHAINED and t["tile"] == tile, (t, tile)
+        b.close()
+
+
+@pytest.mark.parametrize("collision,fene,tile", [("mrt", "upwind_euler", "64x8"), ("bgk", "cholesky_ab2", "64x8"),
+                                                ("mrt", "cholesky_ab2", "64x8"), ("mrt", "cholesky_ab2", "32x16")])
+def test_batches_with_the_papers_schemes_match_single_lattices_bitwise(lb, collision, fene, tile):
     """The paper's MRT collision and Cholesky-log integrator in the chained batch body
     (every instance with the same options) against single chained lattices, bitwise: the
     first step after the fields are set is forward Euler in both (the batch takes it
@@ -110,6 +128,7 @@ def test_batches_with_the_papers_schemes_match_single_lattices_bitwise(lb, colli
     cases = [dict(w, params=dict(w["params"], collision=collision, fene=fene, kappa=0.01))
              for w in small_cases()]
     b = lb.Batch(cases)
+    b.set_tuning(tile, 0, path=lb.PATH_CHAINED)
     total = 0
     for n in (10, 7, 1):
         b.step(n)
@@ -164,8 +183,8 @@ def test_autotuners_pick_a_shape_and_leave_the_state_unchanged(lb):
     b.step(4)
     before = [b.get_fields(i) for i in range(2)]
     res = b.autotune(reps=2)
-    assert res["tile"] in ("32x8", "16x16", "64x8") and res["zchunk"] >= 4 and res["ms_per_step"] > 0
-    assert (res["path"] == lb.PATH_CHAINED) == (res["tile"] == "64x8")
+    assert res["tile"] in ("32x8", "16x16", "64x8", "32x16") and res["zchunk"] >= 4 and res["ms_per_step"] > 0
+    assert (res["path"] == lb.PATH_CHAINED) == (res["tile"] in ("64x8", "32x16"))
     for i in range(2):
         for a, r in zip(b.get_fields(i), before[i]):
             assert np.array_equal(a, r)
@@ -219,8 +238,8 @@ def test_run_to_steady_retires_converged_instances(lb):
     b.close()
 
 
-@pytest.mark.parametrize("scheme", ["default", "paper"])
-def test_batch_instances_match_the_oracle(lb, scheme):
+@pytest.mark.parametrize("scheme,tile", [("default", "64x8"), ("paper", "64x8"), ("default", "32x16")])
+def test_batch_instances_match_the_oracle(lb, scheme, tile):
     """Each instance of one batch of three uneven lattices (one ragged in every direction,
     one with a viscosity ratio, one with a narrow wall gap) against the FP64 oracle run on
     the same seeded inputs: fields to the 1e-5 relative-L2 bar of the single-lattice tests
@@ -244,6 +263,7 @@ def test_batch_instances_match_the_oracle(lb, scheme):
     steps = 300
     b = lb.Batch(cases)
     assert b.get_tuning()["path"] == lb.PATH_CHAINED
+    b.set_tuning(tile, 0, path=lb.PATH_CHAINED)
     b.step(steps)
     dgs = b.diagnostics()
     got = [b.get_fields(i) for i in range(len(cases))]
@@ -255,6 +275,6 @@ def test_batch_instances_match_the_oracle(lb, scheme):
         g = got[i]
         e = {"u": rel(g[1], r[1]), "C": rel(g[2], r[2]), "C-I": rel(g[2] - I6, r[2] - I6),
              "rho": rel(g[0], r[0])}
-        print(f"batch-{scheme}-{i}", " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+        print(f"batch-{scheme}-{tile}-{i}", " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
         assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5, (i, e)
         check_diag(dgs[i], o.diagnostics(), f"batch-{scheme}-{i}", g, r, grid_shape(wl), wl["params"])
