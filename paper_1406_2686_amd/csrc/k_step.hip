@@ -335,9 +335,10 @@ __device__ __forceinline__ unsigned new_state_faults(const DevParams& p, const f
 
 // COLL: 0 BGK, 1 MRT; FENE: 0 upwind/Euler, 1 the Cholesky-log AB2 integrator.  Each option
 // pair is its own instantiation, so the default BGK body keeps the register budget of the
-// plain scheme.
+// plain scheme.  Two workgroups per CU at least: the MRT body otherwise takes 256 VGPRs plus
+// accumulation registers and runs one wavefront per SIMD (44 ms against 26 per step).
 template <int COLL, int FENE>
-__global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __restrict__ h,
+__global__ __launch_bounds__(kBlock, 2) void k_collide(DevParams p, const float* __restrict__ h,
                                                     float* __restrict__ hn,
                                                     const float* __restrict__ D,
                                                     float* __restrict__ Dn,
@@ -413,8 +414,10 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
                 hns[opp(a) * N + n] = post - 6.0f * wgt(a) * rs * wall_cu(a, uw);
             }
         };
-        // equilibrium (with the stress term of eq. MODEtransformation) and source of direction a
-        auto eq_src = [&](int a, float& heq, float& src) {
+        // equilibrium (with the stress term of eq. MODEtransformation) and source of direction
+        // a, and E + S/2 with S/2 joined to the even part before its one rounding (a small
+        // term added to a part already rounded is dropped when below half an ulp of it)
+        auto eq_src = [&](int a, float& heq, float& src, float& base) {
             const float cu = cx(a) * u[0] + cy(a) * u[1] + cz(a) * u[2];
             const float cF = cx(a) * F[0] + cy(a) * F[1] + cz(a) * F[2];
             const Wt w = wsplit(a);
@@ -432,8 +435,10 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
                 st = -4.5f * wgt(a) * (cTc - trs3);
             }
             const float xe = drs + rs * (4.5f * cu * cu - 1.5f * uu);
-            heq = fmaf(w.w, xe, fmaf(w.wl, xe, st)) + fmaf(w.w3, rc, fmaf(w.w3, rce, w.w3l * rc));
+            const float eo = fmaf(w.w3, rc, fmaf(w.w3, rce, w.w3l * rc));
+            heq = fmaf(w.w, xe, fmaf(w.wl, xe, st)) + eo;
             src = wmul(w.w, w.wl, 3.0f * (cF - uFd) + 9.0f * cu * cF);
+            base = fmaf(w.w, xe, fmaf(w.wl, xe, fmaf(0.5f, src, st))) + eo;
         };
         if constexpr (COLL == 1) {
             // MRT (Sec. 2): with every rate 1 except the bulk and shear modes (rate om), the
@@ -442,17 +447,14 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
             // P2 the orthogonal projection on the modes e, 3p_xx, p_ww, p_xy, p_yz, p_xz of
             // the D3Q19 basis (rows 19c^2 - 30, 3c_x^2 - c^2, c_y^2 - c_z^2, c_x c_y, c_y c_z,
             // c_x c_z; squared norms 2394, 36, 12, 4, 4, 4)
-            // f* = h + [S/2 + (1 - om) P2 g - (h - E)]: the increment is formed first and added
-            // to h once (a small term added to a value already rounded at the scale of h is
-            // dropped when below half an ulp of it)
-            float hv[kQ];
+            // E + S/2 as `base`, the mode sum added to it once
+            float base[kQ];
             float pe = 0.f, pxx = 0.f, pww = 0.f, pxy = 0.f, pyz = 0.f, pxz = 0.f;
 #pragma unroll
             for (int a = 0; a < kQ; ++a) {
                 float heq, src;
-                eq_src(a, heq, src);
+                eq_src(a, heq, src, base[a]);
                 const float ha = hs[a * N + n];
-                hv[a] = ha;
                 const float g = ha - heq + 0.5f * src;
                 const int c2 = cx(a) * cx(a) + cy(a) * cy(a) + cz(a) * cz(a);
                 pe += float(19 * c2 - 30) * g;
@@ -478,9 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
                 if (cx(a) * cy(a) != 0) r += float(cx(a) * cy(a)) * pxy;
                 if (cy(a) * cz(a) != 0) r += float(cy(a) * cz(a)) * pyz;
                 if (cx(a) * cz(a) != 0) r += float(cx(a) * cz(a)) * pxz;
-                float heq, src;
-                eq_src(a, heq, src);
-                const float post = hv[a] + (fmaf(0.5f, src, r) - (hv[a] - heq));
+                const float post = base[a] + r;
                 check += post;
                 emit(a, post);
             }
@@ -493,9 +493,10 @@ __global__ __launch_bounds__(kBlock) void k_collide(DevParams p, const float* __
 #pragma unroll
             for (int a = 0; a < kQ; ++a) {
                 const float ha = hv[a];
-                float heq, src;
-                eq_src(a, heq, src);
-                // the increment first, added to h once (see the MRT branch)
+                float heq, src, base;
+                eq_src(a, heq, src, base);
+                // the increment first, added to h once: a small term added to a value already
+                // rounded at the scale of h is dropped when below half an ulp of it
                 const float post = ha + fmaf(cf, src, -om * (ha - heq));
                 check += post;
                 emit(a, post);

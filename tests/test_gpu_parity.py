@@ -2,7 +2,9 @@
 seeded inputs.  Tolerance: relative L2 <= 1e-5 on u and C (and rho), the accuracy
 target for FP32 populations and FP32 C; C - I is reported alongside.  Sizes span several
 blocks with ragged tails; the full 128x64x128 droplet grid is run directly."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -92,6 +94,39 @@ def test_droplet_128x64x128_1000_steps_each_De(lb, De):
     e = report(f"cfg1-1000-De{De:g}", g, r)
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["C-I"] < 1e-5 and e["rho"] < 1e-5, e
     check_diag(dg, do, f"cfg1-1000-De{De:g}", g, r, grid_shape(wl), wl["params"])
+
+
+@pytest.mark.parametrize("De", [0.1, 0.5, 1.0])
+def test_droplet_128x64x128_20000_steps_against_the_stored_oracle_reference(lb, De):
+    """The specified length of the 128x64x128 droplet run: 20,000 steps at each Deborah
+    number of the sweep, against the FP64 oracle's fields stored by
+    tests/golden/droplet_long_reference.py (every 8th node in x and z, every 4th in y, 4096
+    nodes): u, C, C - I and the densities within 1e-5 relative L2 on those nodes; D within
+    1e-5 and the angle within 1e-3 degrees of the oracle's diagnostics; species mass to
+    1e-7 relative."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"droplet_long_De{De:g}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored reference {os.path.basename(path)} (tests/golden/droplet_long_reference.py writes it)")
+    ref = np.load(path)
+    steps = int(ref["step"])
+    od = json.loads(str(ref["diags"]))[str(steps)]
+    wl = workloads.droplet_cfg1(De=De, variant="physics")
+    g = grid_shape(wl)
+    sel = np.zeros((g[2], g[1], g[0]), bool)
+    sel[::8, ::4, ::8] = True
+    sel = sel.ravel()
+    lat = lb.from_workload(wl)
+    lat.step(steps)
+    rho, u, C = lat.get_fields()
+    d = lat.diagnostics()
+    lat.close()
+    cmi = C[:, sel] - I6
+    e = {"u": rel(u[:, sel], ref["u"]), "C": rel(C[:, sel], ref["CmI"] + I6), "C-I": rel(cmi, ref["CmI"]),
+         "rho": rel(rho[:, sel], ref["rho"]), "D": abs(d["D"] - od["D"]), "theta": abs(d["theta_deg"] - od["theta_deg"]),
+         "mass": max(abs(d["mass_A"] - od["mass_A"]) / od["mass_A"], abs(d["mass_B"] - od["mass_B"]) / od["mass_B"])}
+    print(f"cfg1-{steps}-De{De:g}", " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["C-I"] < 1e-5 and e["rho"] < 1e-5, e
+    assert e["D"] < 1e-5 and e["theta"] < 1e-3 and e["mass"] < 1e-7, e
 
 
 @pytest.mark.parametrize("case", ["polyA", "polyB", "visc_ratio", "ragged"])
