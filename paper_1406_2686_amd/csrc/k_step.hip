@@ -335,8 +335,8 @@ __device__ __forceinline__ unsigned new_state_faults(const DevParams& p, const f
 
 // COLL: 0 BGK, 1 MRT; FENE: 0 upwind/Euler, 1 the Cholesky-log AB2 integrator.  Each option
 // pair is its own instantiation, so the default BGK body keeps the register budget of the
-// plain scheme.  Two workgroups per CU at least: the MRT body otherwise takes 256 VGPRs plus
-// accumulation registers and runs one wavefront per SIMD (44 ms against 26 per step).
+// plain scheme.  Two workgroups per CU at least (the MRT body keeps E + S/2 of the 19
+// directions between its two loops and must stay within 256 registers).
 template <int COLL, int FENE>
 __global__ __launch_bounds__(kBlock, 2) void k_collide(DevParams p, const float* __restrict__ h,
                                                     float* __restrict__ hn,
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_collide(DevParams p, const float*
                 float heq, src;
                 eq_src(a, heq, src, base[a]);
                 const float ha = hs[a * N + n];
-                const float g = ha - heq + 0.5f * src;
+                const float g = (ha - base[a]) + src;  // f - E + S/2
                 const int c2 = cx(a) * cx(a) + cy(a) * cy(a) + cz(a) * cz(a);
                 pe += float(19 * c2 - 30) * g;
                 if (3 * cx(a) * cx(a) - c2 != 0) pxx += float(3 * cx(a) * cx(a) - c2) * g;

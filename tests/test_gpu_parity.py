@@ -1,7 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
-seeded inputs.  Tolerance: relative L2 <= 1e-5 on u and C (and rho), the accuracy
-target for FP32 populations and FP32 C; C - I is reported alongside.  Sizes span several
-blocks with ragged tails; the full 128x64x128 droplet grid is run directly."""
+seeded inputs.  Tolerance: relative L2 <= 1e-5 on u, C, C - I and rho, the accuracy
+target for FP32 populations and FP32 C (C - I is the informative part of C, whose norm I
+dominates).  Sizes span several blocks with ragged tails; the full 128x64x128 droplet grid
+is run directly."""
 import json
 import math
 import os
@@ -60,7 +61,7 @@ def test_couette_fenep_16x32x16_4000_steps(lb):
     g, r, dg, do = run_both(lb, wl, 4000)
     e = report("couette4000", g, r)
     assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-6
-    assert e["C-I"] < 1e-4
+    assert e["C-I"] < 1e-5
     assert abs(dg["mass_A"] - do["mass_A"]) < 1e-6 * do["mass_A"]
     # total momentum is ~0 by symmetry: bound the difference by the momentum scale N max|u|
     scale = wl["rho"].size * do["max_u"]
@@ -73,7 +74,7 @@ def test_droplet_128x64x128_full_grid(lb, variant):
     wl = workloads.droplet_cfg1(De=1.0, variant=variant)
     g, r, dg, do = run_both(lb, wl, 100)
     e = report(f"cfg1-{variant}", g, r)
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
     for k in ("mass_A", "mass_B"):
         assert abs(dg[k] - do[k]) < 1e-6 * do[k]
     assert abs(dg["D"] - do["D"]) < 1e-5 and abs(dg["xc"] - do["xc"]) < 1e-6 * do["xc"]
@@ -148,7 +149,7 @@ def test_droplet_long_runs(lb, case):
                                      U=0.008)
     g, r, dg, do = run_both(lb, wl, 1500)
     e = report(f"long-{case}", g, r)
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
     assert abs(dg["D"] - do["D"]) < 1e-5
     check_diag(dg, do, f"long-{case}", g, r, grid_shape(wl), wl["params"])
 
@@ -172,7 +173,7 @@ def test_degenerate_and_ragged_shapes(lb, shape, scheme):
         wl["params"].update(collision="mrt", fene="cholesky_ab2", kappa=0.01, coupling="stress")
     g, r, _, _ = run_both(lb, wl, 60)
     e = report(f"shape{shape}-{scheme}", g, r)
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
 
 
 def test_random_configurations_match_oracle(lb):
@@ -217,7 +218,7 @@ def test_random_configurations_match_oracle(lb):
         o = oracle.from_workload(wl)
         assert o.step(50) == 0, tag
         e = report(tag, g, o.get_fields())
-        assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5, tag
+        assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5, tag
 
 
 def test_zero_steps_returns_initial_fields(lb):
@@ -383,7 +384,7 @@ def test_two_pass_step_matches_oracle(lb, case):
     r = o.get_fields()
     do = o.diagnostics()
     e = report(f"two-pass-{case}", g, r)
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
     assert abs(dg["D"] - do["D"]) < 1e-5
 
 
@@ -446,7 +447,7 @@ def test_chained_step_matches_oracle(lb, case):
     r = o.get_fields()
     do = o.diagnostics()
     e = report(f"chained-{case}", g, r)
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
     assert abs(dg["D"] - do["D"]) < 1e-5
     check_diag(dg, do, f"chained-{case}", g, r, grid_shape(wl), wl["params"])
 
@@ -551,7 +552,7 @@ def test_mrt_collision_matches_oracle(lb, case, path):
     r = o.get_fields()
     do = o.diagnostics()
     e = report(f"mrt-{case}-{path}", g, r)
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
     for k in ("mass_A", "mass_B"):
         assert abs(dg[k] - do[k]) <= 1e-6 * abs(do[k]) + 1e-9
     if case != "couette_tau13":  # (a steady linear profile is the same under both)
@@ -657,7 +658,7 @@ def test_cholesky_ab2_fene_matches_oracle(lb, case, path):
     assert o.step(steps) == 0
     r = o.get_fields()
     e = report(f"cholesky-{case}-{path}", g, r)
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
 
 
 @pytest.mark.parametrize("path", ["chained", "split"])
@@ -680,7 +681,7 @@ def test_mrt_with_cholesky_ab2_matches_oracle(lb, path):
     o = oracle.from_workload(wl)
     assert o.step(400) == 0
     e = report(f"mrt+cholesky-{path}", g, o.get_fields())
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
 
 
 def test_papers_full_scheme_matches_oracle(lb):
@@ -701,7 +702,7 @@ def test_papers_full_scheme_matches_oracle(lb):
     o = oracle.from_workload(wl)
     assert o.step(500) == 0
     e = report("paper-scheme", g, o.get_fields())
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
     assert abs(dg["D"] - o.diagnostics()["D"]) < 1e-5
 
 
@@ -836,7 +837,7 @@ def test_full_size_droplet_sampled_window(lb, collision, fene, coupling):
     e = report(f"full-size window {collision}/{fene}/{coupling}", gs, rs)
     # the sample contains the interface: both phases are present
     assert rs[0][0].max() > 0.5 and rs[0][0].min() < 0.1
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-4
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
 
 
 @pytest.mark.parametrize("case", ["couette", "droplet_polyA", "droplet_polyB_visc"])
@@ -858,7 +859,7 @@ def test_stress_coupling_matches_oracle(lb, case):
         steps = 1500
     g, r, dg, do = run_both(lb, wl, steps)
     e = report(f"stress-{case}", g, r)
-    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5
+    assert e["u"] < 1e-5 and e["C"] < 1e-5 and e["rho"] < 1e-5 and e["C-I"] < 1e-5
     assert abs(dg["D"] - do["D"]) < 1e-5
     if case != "couette":
         # at an interface the two couplings differ (the modulated stress is not uniform):
