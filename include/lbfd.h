@@ -316,6 +316,11 @@ lbfd_status lbfd_batch_get_fields(lbfd_batch* b, int32_t i, double* rho, double*
  * are in out[i].flags).  Re-activates every instance before returning. */
 lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit, int64_t max_steps,
                                      lbfd_diag* out, int64_t* steady_step);
+/* Progress report of lbfd_batch_run_to_steady: after each chunk of `every` steps it calls
+ * fn(steps taken, instances still stepping, user) on the calling thread (fn NULL: none).
+ * fn must not call into the batch. */
+typedef void (*lbfd_progress_fn)(int64_t step, int32_t active, void* user);
+lbfd_status lbfd_batch_set_progress(lbfd_batch* b, lbfd_progress_fn fn, void* user);
 /* Launch-shape autotuner for the batch: both paths, their tiles and a range of z-chunks
  * (state unchanged, as lbfd_autotune). */
 lbfd_status lbfd_batch_autotune(lbfd_batch* b, int32_t reps, lbfd_tuning* best, double* ms_per_step);

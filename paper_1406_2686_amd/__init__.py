@@ -141,6 +141,8 @@ _sig("lbfd_batch_get_fields", [_P, ctypes.c_int32, _D, _D, _D])
 _sig("lbfd_batch_run_to_steady", [_P, ctypes.POINTER(SteadyCrit), _I64, ctypes.POINTER(Diag),
                                   ctypes.POINTER(ctypes.c_int64)])
 _sig("lbfd_batch_autotune", [_P, ctypes.c_int32, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)])
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p)
+_sig("lbfd_batch_set_progress", [_P, PROGRESS_FN, _P])
 _sig("lbfd_batch_instance", [_P, ctypes.c_int32], _P)
 _sig("lbfd_batch_destroy", [_P], None)
 _sig("lbfd_batch_last_error", [_P], ctypes.c_char_p)
@@ -489,14 +491,20 @@ class Batch:
         self._check(_lib.lbfd_batch_get_fields(self._h, i, _dp(rho), _dp(u), _dp(C)))
         return rho, u, C
 
-    def run_to_steady(self, every=100, window=1000, tol=1e-4, max_steps=100000, windows=1):
+    def run_to_steady(self, every=100, window=1000, tol=1e-4, max_steps=100000, windows=1, progress=None):
         """Step until each instance's D moved less than tol over each of the last `windows`
         windows (or max_steps); returns final diagnostics and the steady step per instance
-        (-1 not steady, -2 fault)."""
+        (-1 not steady, -2 fault).  progress: optional callable(step, active) called after
+        each `every` steps."""
         crit = SteadyCrit(int(every), int(window), float(tol), int(windows), 0)
         d = (Diag * self.n)()
         ss = (ctypes.c_int64 * self.n)()
-        self._check(_lib.lbfd_batch_run_to_steady(self._h, ctypes.byref(crit), int(max_steps), d, ss))
+        cb = PROGRESS_FN(lambda step, active, _user: progress(int(step), int(active))) if progress else PROGRESS_FN()
+        self._check(_lib.lbfd_batch_set_progress(self._h, cb, None))
+        try:
+            self._check(_lib.lbfd_batch_run_to_steady(self._h, ctypes.byref(crit), int(max_steps), d, ss))
+        finally:
+            self._check(_lib.lbfd_batch_set_progress(self._h, PROGRESS_FN(), None))
         return [x.to_dict() for x in d], [int(v) for v in ss]
 
 

@@ -37,6 +37,8 @@ struct lbfd_batch {
     hipGraphExec_t exec;
     bool graph_ok;
     bool tables_dirty;
+    lbfd_progress_fn progress = nullptr;  // run_to_steady: called after each chunk of steps
+    void* progress_user = nullptr;
     std::string err;
 };
 
@@ -422,6 +424,7 @@ lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit
         st = lbfd_batch_step(b, n);
         if (st != LBFD_OK && st != LBFD_ENONFINITE && st != LBFD_EEXTENSIBILITY && st != LBFD_ENOTSPD) return st;
         t += n;
+        int32_t left = 0;
         for (int i = 0; i < b->n; ++i) {
             if (!act[i]) continue;
             if (b->inst[i]->flags_seen) {  // a faulting instance is retired, not repaired
@@ -440,7 +443,9 @@ lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit
                 act[i] = 0;
                 steady_step[i] = t;
             }
+            left += act[i] ? 1 : 0;
         }
+        if (b->progress) b->progress(t, left, b->progress_user);
     }
     for (int i = 0; i < b->n; ++i) {
         lbfd_status st = lbfd_diagnostics(b->inst[i], &out[i]);
@@ -448,6 +453,13 @@ lbfd_status lbfd_batch_run_to_steady(lbfd_batch* b, const lbfd_steady_crit* crit
     }
     std::vector<uint8_t> all(b->n, 1);
     return lbfd_batch_set_active(b, all.data());
+}
+
+lbfd_status lbfd_batch_set_progress(lbfd_batch* b, lbfd_progress_fn fn, void* user) {
+    if (!b) return LBFD_EINVAL;
+    b->progress = fn;
+    b->progress_user = user;
+    return LBFD_OK;
 }
 
 lbfd_status lbfd_batch_autotune(lbfd_batch* b, int32_t reps, lbfd_tuning* best, double* ms_per_step) {

@@ -122,7 +122,14 @@ def solve(lb, wls, every=100, window=1000, tol=1e-4, max_steps=20000, chunk=256,
             part = [dict(w, **dict(zip(("rho", "u", "C"), warm_fields(w, *warm[s0 + i]))))
                     for i, w in enumerate(part)]
         b = lb.Batch(part)
-        diags, ss = b.run_to_steady(every=every, window=window, tol=tol, max_steps=max_steps, windows=windows)
+        report = None
+        if progress is not None:
+            def report(step, active, _t0=t0, _n=len(part)):
+                if step % 1000 == 0:
+                    progress(f"  batched: step {step}, {active} of {_n} instances still stepping, "
+                             f"{time.perf_counter() - _t0:.1f} s")
+        diags, ss = b.run_to_steady(every=every, window=window, tol=tol, max_steps=max_steps, windows=windows,
+                                    progress=report)
         for i, (d, s) in enumerate(zip(diags, ss)):
             k = s0 + i
             out["D"][k] = d["D"]

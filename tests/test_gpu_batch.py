@@ -221,8 +221,14 @@ def test_run_to_steady_retires_converged_instances(lb):
     moving = workloads.droplet_shear(nx=48, ny=24, nz=32, R=6.0, G=workloads.G_PHYSICS_1_004,
                                      polymer_phase="A", De=0.5, U=0.03)
     b = lb.Batch([still, moving])
-    diags, ss = b.run_to_steady(every=10, window=20, tol=1e-6, max_steps=200)
+    seen = []
+    diags, ss = b.run_to_steady(every=10, window=20, tol=1e-6, max_steps=200,
+                                progress=lambda step, active: seen.append((step, active)))
     assert ss[0] == 30  # three samples are needed for a window of two intervals
+    # the progress report: after every chunk of steps, with the instances still stepping
+    assert [s for s, _ in seen] == list(range(10, 10 * len(seen) + 1, 10))
+    assert seen[2] == (30, 1) and seen[1] == (20, 2)
+    assert seen[-1][0] == (200 if ss[1] == -1 else ss[1])
     assert diags[0]["step"] == ss[0]
     assert ss[1] == -1 or ss[1] > ss[0]
     assert diags[1]["step"] == (200 if ss[1] == -1 else ss[1])
