@@ -102,6 +102,25 @@ def test_chained_batch_matches_chained_single_lattices_bitwise(lb, tile):
     b.close()
 
 
+@pytest.mark.parametrize("tile", ["64x8", "32x16"])
+def test_single_component_chained_batch_matches_single_lattices_bitwise(lb, tile):
+    """One-component lattices (FENE-P Couette with noise on C, one of them ragged and one
+    narrower than a tile) in the chained batch body against single chained lattices,
+    bitwise: the one-component body runs eight wavefronts, two of which collide the
+    neighbouring rows."""
+    cases = [workloads.couette_fenep(nx=16, ny=32, nz=16, seed=1),
+             workloads.couette_fenep(nx=40, ny=21, nz=9, seed=2, U=0.02),
+             workloads.couette_fenep(nx=96, ny=12, nz=20, seed=3, tau=0.8)]
+    b = lb.Batch(cases)
+    b.set_tuning(tile, 0, path=lb.PATH_CHAINED)
+    b.step(25)
+    ref = singles(lb, cases, 25, lb.PATH_CHAINED)
+    for i in range(len(cases)):
+        for a, r in zip(b.get_fields(i), ref[i]):
+            assert np.array_equal(a, r), (tile, i)
+    b.close()
+
+
 def test_default_chained_tile_follows_the_instance_widths(lb):
     """A new batch runs the chained body on 32x16 tiles when its lattices would leave 64x8
     tiles emptier by a tenth of the lanes or more (32 and 96 nodes wide), else on 64x8."""
