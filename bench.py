@@ -496,8 +496,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the multi-GPU (slab-decomposed) path is a design, "
-              "not part of this build; use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the multi-GPU (slab-decomposed) path is a design "
+              "and is not implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
